@@ -1,0 +1,356 @@
+"""FP64 CPU oracle of the batch non-holonomic trajectory optimizer.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module. It shares no code
+with the HIP path and imports nothing from the product package.
+
+What it computes is the paper's method written out plainly, in float64, with
+every matrix formed explicitly as printed:
+
+* basis (Sec. III-B, eq. 6): 10th-order Bernstein polynomials on tau = t/t_f;
+* stacked matrices (eq. 7a-c): F_o is P repeated m times, obstacle-major;
+* reformulated problem (eq. 8a-c, 9): Q = P''^T P'', A c = b, F c = g(...);
+* Algorithm 1 (Sec. III-D, eqs. 12-16) in its order: x/y QP -> heading QP ->
+  velocity -> (alpha, d) -> (alpha_a, d_a) -> multipliers (eqs. 23-24);
+* the QPs are solved through their KKT systems (eqs. 17, 19) with one LU
+  factorisation shared by the whole batch (eqs. 18, 20);
+* closed forms: velocity (eq. 21), alpha (eq. 22), d as the clipped 1-D
+  least-squares minimiser of the second half of eq. 15, (alpha_a, d_a) as in
+  eq. 16;
+* meta-costs (eqs. 25, 26) and the heading post-filter (Sec. III intro).
+
+Readings where the paper is silent or garbled (documented with the design):
+boundary rows, cold start, residual norms, d >= 1 rather than the printed
+[0, 1] clip, etc. -- see the module functions.
+
+Batch convention: goals are columns (the paper's [q_1 | ... | q_l]).
+"""
+from __future__ import annotations
+
+from math import comb
+
+import numpy as np
+import scipy.linalg
+
+# ----------------------------------------------------------------- basis (eq. 6)
+
+
+def bernstein_matrices(n_coef: int, n_time: int, t_f: float):
+    """P, P_dot, P_ddot (n_time x n_coef), Bernstein degree n_coef-1 on tau = t/t_f.
+
+    Time grid: n_time samples linspace(0, t_f) inclusive. Derivatives are the
+    exact derivatives of the Bernstein polynomials with respect to t, i.e. the
+    tau-derivatives scaled by 1/t_f and 1/t_f^2.
+    """
+    deg = n_coef - 1
+    tau = np.linspace(0.0, 1.0, n_time)
+
+    def B(d, k):
+        if k < 0 or k > d:
+            return np.zeros_like(tau)
+        return comb(d, k) * tau ** k * (1.0 - tau) ** (d - k)
+
+    P = np.stack([B(deg, k) for k in range(n_coef)], axis=1)
+    Pd = np.stack([deg * (B(deg - 1, k - 1) - B(deg - 1, k)) for k in range(n_coef)], axis=1) / t_f
+    Pdd = np.stack([deg * (deg - 1) * (B(deg - 2, k - 2) - 2.0 * B(deg - 2, k - 1) + B(deg - 2, k))
+                    for k in range(n_coef)], axis=1) / t_f ** 2
+    return P, Pd, Pdd
+
+
+def time_grid(n_time: int, t_f: float) -> np.ndarray:
+    return np.linspace(0.0, t_f, n_time)
+
+
+# ---------------------------------------------------- boundary conditions (eq. 8b)
+
+
+def boundary_matrices(P, Pd, Pdd):
+    """Rows of A for each axis (reading of the boundary set C_b of eq. 1c).
+
+    x:   x(0), x'(0), x''(0), x(t_f)
+    y:   y(0), y'(0), y''(0), y(t_f), y'(t_f) = 0, y''(t_f) = 0
+    psi: psi(0), psi'(0), psi(t_f) = 0, psi'(t_f) = 0
+    """
+    A_x = np.stack([P[0], Pd[0], Pdd[0], P[-1]])
+    A_y = np.stack([P[0], Pd[0], Pdd[0], P[-1], Pd[-1], Pdd[-1]])
+    A_psi = np.stack([P[0], Pd[0], P[-1], Pd[-1]])
+    return A_x, A_y, A_psi
+
+
+def boundary_values(ego, goals):
+    """b_x (4 x B), b_y (6 x B), b_psi (4 x B) from the ego state and goal positions.
+
+    ego = (x0, y0, vx0, vy0, ax0, ay0, psi0, psidot0); goals = (x_f, y_f) per goal.
+    Final lateral velocity/acceleration and final heading/heading rate are 0.
+    """
+    ego = np.asarray(ego, np.float64)
+    goals = np.asarray(goals, np.float64)
+    B = goals.shape[0]
+    one = np.ones(B)
+    b_x = np.stack([ego[0] * one, ego[2] * one, ego[4] * one, goals[:, 0]])
+    b_y = np.stack([ego[1] * one, ego[3] * one, ego[5] * one, goals[:, 1], 0 * one, 0 * one])
+    b_psi = np.stack([ego[6] * one, ego[7] * one, 0 * one, 0 * one])
+    return b_x, b_y, b_psi
+
+
+# ------------------------------------------------------ problem data (eqs. 7, 9)
+
+
+def obstacle_predictions(obs, t):
+    """xi_x, xi_y stacked obstacle-major (m*n,): constant-velocity prediction x_j + vx_j t."""
+    obs = np.asarray(obs, np.float64).reshape(-1, 4)
+    xi_x = (obs[:, 0:1] + obs[:, 2:3] * t[None, :]).reshape(-1)
+    xi_y = (obs[:, 1:2] + obs[:, 3:4] * t[None, :]).reshape(-1)
+    return xi_x, xi_y
+
+
+def build_F(P, Pd, Pdd, m):
+    """F = blkdiag(F_ax, F_ax), F_ax = [F_o; P''; P'], F_o = P stacked m times (eq. 9, Sec. III-B)."""
+    F_o = np.concatenate([P] * m, axis=0) if m > 0 else np.zeros((0, P.shape[1]))
+    F_ax = np.concatenate([F_o, Pdd, Pd], axis=0)
+    Z = np.zeros_like(F_ax)
+    F = np.block([[F_ax, Z], [Z, F_ax]])
+    return F, F_ax
+
+
+def build_g(xi_x, xi_y, a, b, d, alpha, d_a, alpha_a, v, psi):
+    """g_l of eq. 9, one column per goal. d, alpha: (m*n, B); d_a, alpha_a, v, psi: (n, B)."""
+    g_x = np.concatenate([xi_x[:, None] + a * d * np.cos(alpha),
+                          d_a * np.cos(alpha_a),
+                          v * np.cos(psi)], axis=0)
+    g_y = np.concatenate([xi_y[:, None] + b * d * np.sin(alpha),
+                          d_a * np.sin(alpha_a),
+                          v * np.sin(psi)], axis=0)
+    return np.concatenate([g_x, g_y], axis=0)
+
+
+# ------------------------------------------------------------- the optimizer
+
+
+class Problem:
+    """Constant data of one (n_time, t_f, m) shape: basis, F, KKT factorisations (Remark 1)."""
+
+    def __init__(self, n_time, t_f, m, params):
+        p = params
+        self.N = N = int(p["n_coef"])
+        self.n = n_time
+        self.t_f = float(t_f)
+        self.m = m
+        self.rho = float(p["rho"])
+        self.a, self.b = float(p["a"]), float(p["b"])
+        self.v_min, self.v_max = float(p["v_min"]), float(p["v_max"])
+        self.a_max = float(p["a_max"])
+        self.psi_max = float(p["psi_max"])
+        self.t = time_grid(n_time, t_f)
+        self.P, self.Pd, self.Pdd = bernstein_matrices(N, n_time, t_f)
+        # cost matrix: sum of squared accelerations (eq. 8a)
+        self.Q = self.Pdd.T @ self.Pdd
+        self.A_x, self.A_y, self.A_psi = boundary_matrices(self.P, self.Pd, self.Pdd)
+        nx, ny = self.A_x.shape[0], self.A_y.shape[0]
+        self.A = np.block([[self.A_x, np.zeros((nx, N))], [np.zeros((ny, N)), self.A_y]])
+        self.F, self.F_ax = build_F(self.P, self.Pd, self.Pdd, m)
+        rho = self.rho
+        QQ = np.block([[self.Q, np.zeros((N, N))], [np.zeros((N, N)), self.Q]])
+        ne = self.A.shape[0]
+        # eq. 17: [[Q + rho F^T F, A^T], [A, 0]]
+        self.Q_xy = np.block([[QQ + rho * self.F.T @ self.F, self.A.T], [self.A, np.zeros((ne, ne))]])
+        # eq. 19: [[Q + rho P^T P, A^T], [A, 0]]
+        npsi = self.A_psi.shape[0]
+        self.Q_psi = np.block([[self.Q + rho * self.P.T @ self.P, self.A_psi.T],
+                               [self.A_psi, np.zeros((npsi, npsi))]])
+        # cold start: the boundary-only minimum-acceleration QP
+        self.Q_0 = np.block([[QQ, self.A.T], [self.A, np.zeros((ne, ne))]])
+        # one factorisation each, shared by every goal (eqs. 18, 20)
+        self.lu_xy = scipy.linalg.lu_factor(self.Q_xy)
+        self.lu_psi = scipy.linalg.lu_factor(self.Q_psi)
+        self.lu_0 = scipy.linalg.lu_factor(self.Q_0)
+
+
+def _xy_rhs_b(prob, ego, goals):
+    b_x, b_y, b_psi = boundary_values(ego, goals)
+    return np.concatenate([b_x, b_y], axis=0), b_psi
+
+
+def solve_xy(prob, g, lam_xy, b_xy):
+    """Step (12) through eq. 17/18: returns c_x, c_y (N x B each) and the full KKT solution."""
+    rhs = np.concatenate([prob.rho * prob.F.T @ g + lam_xy, b_xy], axis=0)
+    sol = scipy.linalg.lu_solve(prob.lu_xy, rhs)
+    N = prob.N
+    return sol[:N], sol[N:2 * N], sol
+
+
+def solve_psi(prob, theta, lam_psi, b_psi):
+    """Step (13) with the convex surrogate, through eq. 19/20."""
+    rhs = np.concatenate([prob.rho * prob.P.T @ theta + lam_psi, b_psi], axis=0)
+    sol = scipy.linalg.lu_solve(prob.lu_psi, rhs)
+    return sol[:prob.N], sol
+
+
+def project_velocity(prob, xd, yd):
+    """Eq. 21: v = clip(sqrt(xd^2 + yd^2), v_min, v_max)."""
+    return np.clip(np.sqrt(xd ** 2 + yd ** 2), prob.v_min, prob.v_max)
+
+
+def project_obstacles(prob, x, y, xi_x, xi_y):
+    """Step (15): alpha by eq. 22; d as the 1-D least-squares minimiser over d >= 1.
+
+    x, y: (n, B). Returns alpha, d of shape (m*n, B), obstacle-major rows.
+    The printed clip to [0, 1] contradicts the constraint d >= 1 stated with
+    eq. 4 and the feasible set of eq. 15; d >= 1 is used.
+    """
+    m = prob.m
+    a, b = prob.a, prob.b
+    X = np.tile(x, (m, 1))
+    Y = np.tile(y, (m, 1))
+    dx = X - xi_x[:, None]
+    dy = Y - xi_y[:, None]
+    alpha = np.arctan2(a * dy, b * dx)
+    ca, sa = np.cos(alpha), np.sin(alpha)
+    # minimiser of sum (dx - a d cos)^2 + (dy - b d sin)^2 over d (no bound), then d >= 1
+    d_unc = (a * dx * ca + b * dy * sa) / (a ** 2 * ca ** 2 + b ** 2 * sa ** 2)
+    d = np.maximum(1.0, d_unc)
+    return alpha, d, d_unc
+
+
+def project_acceleration(prob, xdd, ydd):
+    """Step (16): alpha_a = atan2(y'', x''); d_a = 1-D minimiser clipped to d_a <= a_max."""
+    alpha_a = np.arctan2(ydd, xdd)
+    d_unc = xdd * np.cos(alpha_a) + ydd * np.sin(alpha_a)
+    d_a = np.minimum(prob.a_max, d_unc)
+    return alpha_a, d_a
+
+
+class State:
+    """Per-goal iterate: coefficients, multipliers and the split variables."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def _sweep(prob, st, xi_x, xi_y, b_psi, do_psi_qp):
+    """Steps (13)-(16) from the current c_x, c_y: heading QP (optional), v, (alpha, d), (alpha_a, d_a)."""
+    P, Pd, Pdd = prob.P, prob.Pd, prob.Pdd
+    xd, yd = Pd @ st.c_x, Pd @ st.c_y
+    st.theta = np.arctan2(yd, xd)
+    if do_psi_qp:
+        st.c_psi, _ = solve_psi(prob, st.theta, st.lam_psi, b_psi)
+    st.v = project_velocity(prob, xd, yd)
+    x, y = P @ st.c_x, P @ st.c_y
+    st.alpha, st.d, st.d_unc = project_obstacles(prob, x, y, xi_x, xi_y)
+    st.alpha_a, st.d_a = project_acceleration(prob, Pdd @ st.c_x, Pdd @ st.c_y)
+    st.psi = P @ st.c_psi
+
+
+def _g(prob, st, xi_x, xi_y):
+    return build_g(xi_x, xi_y, prob.a, prob.b, st.d, st.alpha, st.d_a, st.alpha_a, st.v, st.psi)
+
+
+def residuals(prob, st, g):
+    """Components of F c - g (eq. 8c) per goal, plus the heading surrogate residual.
+
+    r_obs: 2-norm over the obstacle rows of both axes; r_acc: over the P'' rows;
+    r_nh: over the P' rows; r_psi: ||atan2(y', x') - P c_psi||.
+    """
+    m, n = prob.m, prob.n
+    c = np.concatenate([st.c_x, st.c_y], axis=0)
+    r = prob.F @ c - g
+    L = (m + 2) * n
+    rx, ry = r[:L], r[L:]
+    r_obs = np.sqrt(np.sum(rx[:m * n] ** 2, 0) + np.sum(ry[:m * n] ** 2, 0))
+    r_acc = np.sqrt(np.sum(rx[m * n:(m + 1) * n] ** 2, 0) + np.sum(ry[m * n:(m + 1) * n] ** 2, 0))
+    r_nh = np.sqrt(np.sum(rx[(m + 1) * n:] ** 2, 0) + np.sum(ry[(m + 1) * n:] ** 2, 0))
+    r_psi = np.sqrt(np.sum((st.theta - prob.P @ st.c_psi) ** 2, 0))
+    return np.stack([r_obs, r_acc, r_nh, r_psi])
+
+
+def cold_start(prob, ego, goals):
+    """c^0 = argmin 1/2 c^T Q c s.t. A c = b (boundary-only minimum acceleration), lambda^0 = 0."""
+    b_xy, b_psi = _xy_rhs_b(prob, ego, goals)
+    B = goals.shape[0]
+    N = prob.N
+    rhs = np.concatenate([np.zeros((2 * N, B)), b_xy], axis=0)
+    sol = scipy.linalg.lu_solve(prob.lu_0, rhs)
+    return sol[:N], sol[N:2 * N]
+
+
+def solve(prob, ego, obs, goals, iters, init=None, record=False):
+    """Run Algorithm 1 for ``iters`` iterations on every goal of one scene.
+
+    init: None for the cold start, or a dict with c_x, c_y, c_psi, lam_x,
+    lam_y, lam_psi (each N x B) to resume from a stored iterate (then the
+    heading QP is not re-run before the first iteration; the stored c_psi is
+    used as is).
+
+    Returns a State with c_*, lam_*, resid (4 x B, after the last iteration)
+    and, if ``record``, hist (iters x 4 x B).
+    """
+    ego = np.asarray(ego, np.float64)
+    goals = np.asarray(goals, np.float64).reshape(-1, 2)
+    B = goals.shape[0]
+    N = prob.N
+    xi_x, xi_y = obstacle_predictions(obs, prob.t)
+    b_xy, b_psi = _xy_rhs_b(prob, ego, goals)
+    if init is None:
+        c_x, c_y = cold_start(prob, ego, goals)
+        st = State(c_x=c_x, c_y=c_y, c_psi=np.zeros((N, B)),
+                   lam_x=np.zeros((N, B)), lam_y=np.zeros((N, B)), lam_psi=np.zeros((N, B)))
+        _sweep(prob, st, xi_x, xi_y, b_psi, do_psi_qp=True)
+    else:
+        st = State(**{k: np.array(init[k], np.float64) for k in
+                      ("c_x", "c_y", "c_psi", "lam_x", "lam_y", "lam_psi")})
+        _sweep(prob, st, xi_x, xi_y, b_psi, do_psi_qp=False)
+    g = _g(prob, st, xi_x, xi_y)
+    hist = []
+    st.resid = np.full((4, B), np.nan)
+    rho = prob.rho
+    for _ in range(iters):
+        lam_xy = np.concatenate([st.lam_x, st.lam_y], axis=0)
+        # (12) x/y QP with the g of the previous iteration
+        st.c_x, st.c_y, _ = solve_xy(prob, g, lam_xy, b_xy)
+        # (13)-(16)
+        _sweep(prob, st, xi_x, xi_y, b_psi, do_psi_qp=True)
+        g = _g(prob, st, xi_x, xi_y)
+        # multipliers (eqs. 23, 24)
+        c = np.concatenate([st.c_x, st.c_y], axis=0)
+        lam_xy = lam_xy - rho * prob.F.T @ (prob.F @ c - g)
+        st.lam_x, st.lam_y = lam_xy[:N], lam_xy[N:]
+        # eq. 24 with the residual taken as (model - target), P c_psi - theta, the
+        # same orientation as F c - g in eq. 23: the printed (theta - P c_psi)
+        # makes the heading multiplier grow geometrically.
+        st.lam_psi = st.lam_psi - rho * prob.P.T @ (prob.P @ st.c_psi - st.theta)
+        st.resid = residuals(prob, st, g)
+        if record:
+            hist.append(st.resid.copy())
+    if record:
+        st.hist = np.array(hist)
+    return st
+
+
+# ------------------------------------------------------------ ranking (Sec. III-F)
+
+
+def meta_cost(prob, c_x, c_y, c_psi, kind=0, v_ref=None, w1=1.0, w2=1.0, y_rl=0.0):
+    """Meta-cost per goal: eq. 25 (kind 0, v_ref = v_cruise) or eq. 26 (kind 1, v_ref = v_max).
+
+    v(t) is the speed of the final trajectory, sqrt(x'^2 + y'^2). A goal whose
+    heading P c_psi exceeds psi_max in magnitude at any sample is discarded
+    (cost +inf), the post-filter of Sec. III.
+    """
+    v = np.sqrt((prob.Pd @ c_x) ** 2 + (prob.Pd @ c_y) ** 2)
+    if kind == 0:
+        cost = np.sum((v - v_ref) ** 2, axis=0)
+    else:
+        y = prob.P @ c_y
+        cost = np.sum(w1 * (v - v_ref) ** 2 + w2 * (y - y_rl) ** 2, axis=0)
+    psi = prob.P @ c_psi
+    bad = np.max(np.abs(psi), axis=0) > prob.psi_max
+    return np.where(bad, np.inf, cost)
+
+
+def best_goal(cost):
+    """Lowest index attaining the minimum finite cost, -1 if every goal is filtered."""
+    cost = np.asarray(cost, np.float64)
+    finite = np.isfinite(cost)
+    if not finite.any():
+        return -1
+    return int(np.flatnonzero(cost == np.min(cost[finite]))[0])
