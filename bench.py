@@ -1,0 +1,144 @@
+"""Benchmark: one step = one whole pass of the hot path over the dense workload.
+
+Workload: 1 scene x 1024 goals, 50 obstacles, 6 lanes, T = 100 samples over
+10 s, 100 iterations of Algorithm 1 per goal (cold start), then meta-cost
+scoring and argmin. Operator setup (the FP64 KKT inverses) is done once before
+the timed region: it depends only on (T, m), not on the batch.
+
+Prints ONE JSON line. `value` is goal-trajectories x iterations per second on
+this GPU with inputs resident in HBM. `roofline` is for the dominant kernel
+(the fused AM kernel), from its average duration measured with HIP events on
+the stream it is launched on; `cpu_baseline` is the FP64 oracle on one core
+over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_COEF = 11
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
+
+
+def algorithmic_flops_per_goal_iter(n, m, N=N_COEF):
+    """Algorithmic FP32 work of one AM iteration of one goal (FMA = 2).
+
+    contractions 28 N n (basis evaluation 12 N n, x/y transposed contraction
+    12 N n, heading 4 N n) + 11x11 applies 16 N^2 + element-wise 30 n +
+    obstacle test 8 m n.
+    """
+    return 28 * N * n + 16 * N * N + 30 * n + 8 * m * n
+
+
+def cpu_baseline(scene, iters, n_goals_sample):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import traj_oracle as O
+    from paper_2109_10392_amd import scenes as S
+    with threadpool_limits(1):
+        prob = O.Problem(scene.n_time, scene.t_f, scene.obs.shape[0], S.DEFAULT_PARAMS)
+        t0 = time.perf_counter()
+        O.solve(prob, scene.ego, scene.obs, scene.goals[:n_goals_sample], iters)
+        dt = time.perf_counter() - t0
+    return {"value": n_goals_sample * iters / dt, "unit": "goal-trajectories*iters/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_goals_sample} of the 1024 goals of the same scene, {iters} iterations, FP64 NumPy, "
+                      f"1 BLAS thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-goals", type=int, default=160)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "goals are independent, so a multi-GPU run would shard scenes with no exchange inside the loop.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2109_10392_amd import scenes as S
+    from paper_2109_10392_amd import traj as T
+
+    torch.cuda.set_device(0)
+    batch = S.workload_dense(args.seed)
+    sc = batch.scenes[0]
+    n, m, B = sc.n_time, sc.obs.shape[0], batch.n_goals
+    solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(B)
+    v_ref = torch.tensor([float(sc.ego[2])], device="cuda")
+    cost = torch.zeros(B, device="cuda")
+    best = torch.zeros(1, device="cuda", dtype=torch.int32)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        solver.solve(db, st, args.iters)
+        if ev is not None:
+            ev[1].record()
+        solver.score(db, st, v_ref, cost, best)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for k in range(args.steps):
+        step(evs[k])
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    solve_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_per_step = total_ms / args.steps
+    value = B * args.iters * args.steps / (total_ms / 1e3)
+    solve_avg_s = sum(solve_ms) / len(solve_ms) / 1e3
+    flops = algorithmic_flops_per_goal_iter(n, m) * B * args.iters
+    achieved = flops / solve_avg_s / 1e12
+    out = {
+        "metric": "goal-trajectories*iters/s",
+        "value": value,
+        "unit": "goal-trajectories*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dense highway scene: 1 scene x 1024 goals, 50 obstacles, 6 lanes, "
+                               "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
+                   "goals": B, "obstacles": m, "n_time": n, "iters": args.iters, "seed": args.seed},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_am (fused AM solve)", "kernel_ms": solve_avg_s * 1e3,
+                     "algorithmic_flop_per_launch": flops},
+        "best_goal": int(best.item()),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, args.iters, args.cpu_goals)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * traj.h -- C-ABI of the MI355X (gfx950) batched non-holonomic trajectory optimizer.
+ *
+ * Method: Adajania et al., "Multi-Modal Model Predictive Control through Batch
+ * Non-Holonomic Trajectory Optimization" (arXiv 2109.10392). Many goal-directed
+ * instances of the problem of eq. (1a-e) are solved at once by the alternating
+ * minimisation of Algorithm 1 (Sec. III-D) on the multi-convex reformulation of
+ * eqs. (8a-c), then ranked by the meta-costs of Sec. III-F.
+ *
+ * Conventions for every entry point
+ *   - Return value: TRAJ_OK (0) or a negative TRAJ_E_* code; traj_last_error()
+ *     then returns a message for the calling thread. No C++ exception crosses
+ *     this boundary.
+ *   - "device" pointers are HIP device memory owned by the caller (for example
+ *     PyTorch tensors); "host" pointers are ordinary host memory read during
+ *     the call only. The handle owns only its operator tables.
+ *   - stream is a hipStream_t (NULL = the null stream). Solve and score enqueue
+ *     kernels on it and return without synchronising; they do not allocate and
+ *     do not read device memory on the host.
+ *   - A handle must not be used from two host threads at once.
+ *   - Layouts: goal index fastest. c and lam are [3][11][n_goals] float
+ *     (axis 0 = x, 1 = y, 2 = heading psi; then the 11 Bernstein coefficients).
+ */
+#ifndef TRAJ_H
+#define TRAJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRAJ_OK 0
+#define TRAJ_E_INVAL (-1) /* bad argument: null pointer, size, non-finite parameter, ... */
+#define TRAJ_E_SHAPE (-2) /* shape index out of range / not set up                    */
+#define TRAJ_E_HIP (-3)   /* HIP runtime error (message in traj_last_error)             */
+#define TRAJ_E_NOMEM (-4) /* device allocation failed (setup only)                      */
+
+/* traj_solve_batch flags */
+#define TRAJ_INIT_COLD 0x0u       /* cold start (boundary-only minimum-acceleration QP)      */
+#define TRAJ_INIT_FROM_STATE 0x1u /* start from (c, lam) in the state (resume, warm start)   */
+
+#define TRAJ_N_COEF 11 /* Bernstein degree 10: coefficients per axis */
+
+/* Solver constants shared by every instance of the batch (the Note after eq. 1
+ * and Remark 1: bounds and obstacles are common to all goals). */
+typedef struct {
+  int32_t n_coef; /* must be TRAJ_N_COEF */
+  float rho;      /* penalty weight rho_xy of eq. 10, also used for the heading block (eq. 13) */
+  float a, b;     /* obstacle ellipse semi-axes incl. ego inflation (eq. 1e); > 0 */
+  float v_min, v_max; /* velocity bounds (eq. 1d); 0 < v_min <= v_max (eq. 21 needs v_min > 0) */
+  float a_max;        /* acceleration bound (eq. 1d, eq. 5); > 0 */
+  float psi_max;      /* heading post-filter bound in radians (Sec. III, assumption 2) */
+} traj_params;
+
+/* One horizon/obstacle-count combination. The operator tables depend on both:
+ * F_o stacks P once per obstacle (eq. 7 and the text after it), so F^T F and
+ * the KKT inverses of eqs. 17/19 change with m. */
+typedef struct {
+  int32_t n_time; /* samples of the horizon, 11 <= n_time <= 192, t_i = i t_f/(n_time-1) */
+  float t_f;      /* horizon length in seconds, > 0 */
+  int32_t n_obs;  /* obstacles m of every scene using this shape, 0 <= m <= 64 */
+} traj_shape;
+
+/* A batch of scenes. Scene s owns goals [goal_off[s], goal_off[s+1]) and
+ * obstacles [obs_off[s], obs_off[s+1]); obs_off[s+1]-obs_off[s] must equal the
+ * n_obs of shape shape_id[s]. All arrays are device memory. */
+typedef struct {
+  int32_t n_scenes;
+  int32_t n_goals;         /* == goal_off[n_scenes] */
+  const int32_t *goal_off; /* device [n_scenes+1], non-decreasing, goal_off[0] = 0 */
+  const int32_t *obs_off;  /* device [n_scenes+1] */
+  const int32_t *shape_id; /* device [n_scenes], index into the shapes given to traj_setup */
+  const float *ego;  /* device [n_scenes][8]: x0, y0, vx0, vy0, ax0, ay0, psi0, psidot0 */
+  const float *obs;  /* device [n_obs_total][4]: x, y, vx, vy at t = 0 (constant velocity, Sec. III assumption 3) */
+  const float *goal; /* device [n_goals][2]: x_f, y_f; final lateral velocity/acceleration and heading are 0 */
+} traj_batch;
+
+/* Iterate of every goal. With TRAJ_INIT_FROM_STATE, c and lam are read as the
+ * starting point; on return they hold the last iterate. */
+typedef struct {
+  float *c;       /* device [3][11][n_goals] */
+  float *lam;     /* device [3][11][n_goals] */
+  float *resid;   /* device [4][n_goals]: r_obs, r_acc, r_nh, r_psi after the last iteration (may be NULL) */
+  int32_t *iters; /* device [n_goals]: iterations performed (may be NULL) */
+} traj_state;
+
+/* Meta-cost of Sec. III-F. */
+typedef struct {
+  int32_t kind;       /* 0: cruise, eq. 25; 1: high speed near the right lane, eq. 26 */
+  const float *v_ref; /* device [n_scenes]: v_cruise (kind 0) or v_max (kind 1) */
+  float w1, w2;       /* weights of eq. 26 (ignored for kind 0) */
+  const float *y_rl;  /* device [n_scenes]: lateral position of the right lane (kind 1; may be NULL for kind 0) */
+} traj_metacost;
+
+/*
+ * traj_setup -- build the constant operators of every shape (Remark 1; eqs. 17-20:
+ * the left-hand sides do not depend on the batch index, so one inverse serves
+ * every goal). Bernstein basis, Gram matrices and the KKT matrices of the x, y,
+ * heading and cold-start systems are formed and inverted in FP64 on the GPU;
+ * FP32 tables are derived from them. Allocates the handle's device memory (the
+ * only allocation of the library) and synchronises the stream before returning.
+ *   params: host, copied. shapes: host [n_shapes], copied; 1 <= n_shapes <= 4096.
+ *   handle_out: host, receives the handle.
+ * Errors: TRAJ_E_INVAL for bad parameters or shapes, TRAJ_E_NOMEM, TRAJ_E_HIP.
+ */
+int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes, void *stream,
+               void **handle_out);
+
+/*
+ * traj_solve_batch -- run `iters` iterations of Algorithm 1 on every goal of the
+ * batch: x/y QP with the shared inverse (eq. 12 via eq. 18), heading QP with the
+ * convex surrogate (eq. 13 via eq. 20), velocity (eq. 21), obstacle polar
+ * variables (eq. 22 and the clipped 1-D minimiser of eq. 15), acceleration polar
+ * variables (eq. 16), multipliers (eqs. 23-24).
+ *   flags: TRAJ_INIT_COLD or TRAJ_INIT_FROM_STATE.
+ *   tol: <= 0 runs exactly `iters` iterations; > 0 stops a goal at the first
+ *        multiple of 5 iterations where max(r_obs, r_acc, r_nh) <= tol.
+ *   iters: 0 <= iters <= 100000. n_goals == 0 is a no-op.
+ * Shape mismatches found on the device (unknown shape id, wrong obstacle count)
+ * set that scene's residuals to NaN; nothing aborts.
+ * Errors: TRAJ_E_INVAL (null pointers, negative sizes), TRAJ_E_HIP.
+ */
+int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, int iters, float tol,
+                     uint32_t flags, void *stream);
+
+/*
+ * traj_score -- meta-cost per goal (eq. 25 or 26, v(t) = |(x'(t), y'(t))| of the
+ * final coefficients) with the heading post-filter (cost = +inf when
+ * max_t |psi(t)| > psi_max, Sec. III assumption 2), then per scene the lowest
+ * index attaining the minimum finite cost.
+ *   cost: device [n_goals]. best: device [n_scenes], index within the scene, -1
+ *   if every goal of the scene is filtered.
+ * Errors: TRAJ_E_INVAL, TRAJ_E_HIP.
+ */
+int traj_score(void *handle, const traj_batch *batch, const traj_state *state, const traj_metacost *mc,
+               float *cost, int32_t *best, void *stream);
+
+/* traj_destroy -- free the handle's device memory. NULL is a no-op. */
+int traj_destroy(void *handle);
+
+/* traj_last_error -- message of the last failing call on this thread ("" if none). */
+const char *traj_last_error(void);
+
+/*
+ * traj_debug_operators -- copy one shape's operator tables to host memory for
+ * verification against an independent reference. Synchronises the stream.
+ *   out_f64: host, 5 * 17 * 17 doubles: the inverses of the x, y, heading,
+ *            cold-start x and cold-start y KKT matrices (eqs. 17 and 19 split
+ *            per axis), each stored row-major in a 17x17 block (top-left used).
+ *   out_f32: host, traj_debug_table_size(handle, shape) floats (see the layout
+ *            note in the implementation). Either pointer may be NULL.
+ */
+int traj_debug_operators(void *handle, int shape, double *out_f64, float *out_f32, void *stream);
+int traj_debug_table_size(void *handle, int shape);
+
+/*
+ * traj_debug_reduce -- lane-layout check of the cross-lane reductions the solver
+ * uses for its contractions over time. in: device [r][64] floats (value i of
+ * lane l at in[i*64 + l]); out: device [64]. r = 32: out[l] = sum over lanes of
+ * value l/2; r = 16: out[l] = sum over lanes of value l/4. Asynchronous.
+ */
+int traj_debug_reduce(const float *in, float *out, int r, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAJ_H */

@@ -301,7 +301,7 @@ def solve(prob, ego, obs, goals, iters, init=None, record=False):
         _sweep(prob, st, xi_x, xi_y, b_psi, do_psi_qp=False)
     g = _g(prob, st, xi_x, xi_y)
     hist = []
-    st.resid = np.full((4, B), np.nan)
+    st.resid = residuals(prob, st, g)  # of the starting point, replaced after each iteration
     rho = prob.rho
     for _ in range(iters):
         lam_xy = np.concatenate([st.lam_x, st.lam_y], axis=0)

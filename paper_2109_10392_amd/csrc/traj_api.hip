@@ -1,0 +1,255 @@
+// C-ABI of libtraj: argument validation, handle ownership, kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "traj_internal.h"
+
+namespace traj {
+hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream);
+}
+
+namespace {
+
+using traj::ShapeDesc;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(TRAJ_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Handle {
+  traj_params p;
+  std::vector<ShapeDesc> shapes;
+  ShapeDesc* d_shapes = nullptr;
+  float* d_tables = nullptr;
+  double* d_tables64 = nullptr;
+  int max_n = 0, max_m = 0;
+  size_t table_floats = 0;
+};
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
+
+traj::SolverConst consts(const traj_params& p) {
+  traj::SolverConst k;
+  k.rho = p.rho;
+  k.a = p.a;
+  k.b = p.b;
+  k.v_min = p.v_min;
+  k.v_max = p.v_max;
+  k.a_max = p.a_max;
+  k.psi_max = p.psi_max;
+  return k;
+}
+
+int check_batch(const Handle* h, const traj_batch* b) {
+  if (b == nullptr) return fail(TRAJ_E_INVAL, "batch is NULL");
+  if (b->n_scenes < 0 || b->n_goals < 0) return fail(TRAJ_E_INVAL, "negative batch size");
+  if (b->n_scenes == 0 && b->n_goals > 0) return fail(TRAJ_E_INVAL, "goals without scenes");
+  if (b->n_goals == 0 && b->n_scenes == 0) return TRAJ_OK;
+  if (!b->goal_off || !b->obs_off || !b->shape_id || !b->ego || !b->goal)
+    return fail(TRAJ_E_INVAL, "batch has a NULL device array");
+  if (h->max_m > 0 && b->obs == nullptr) return fail(TRAJ_E_INVAL, "batch.obs is NULL");
+  return TRAJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* traj_last_error(void) { return g_err.c_str(); }
+
+int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes, void* stream, void** handle_out) {
+  g_err.clear();
+  if (params == nullptr || shapes == nullptr || handle_out == nullptr)
+    return fail(TRAJ_E_INVAL, "traj_setup: NULL argument");
+  *handle_out = nullptr;
+  const traj_params& p = *params;
+  if (p.n_coef != TRAJ_N_COEF) return fail(TRAJ_E_INVAL, "n_coef must be %d (got %d)", TRAJ_N_COEF, p.n_coef);
+  if (!finite_pos(p.rho) || !finite_pos(p.a) || !finite_pos(p.b) || !finite_pos(p.v_min) || !finite_pos(p.v_max) ||
+      !finite_pos(p.a_max) || !finite_pos(p.psi_max))
+    return fail(TRAJ_E_INVAL, "parameters must be finite and positive");
+  if (p.v_min > p.v_max) return fail(TRAJ_E_INVAL, "v_min > v_max");
+  if (n_shapes < 1 || n_shapes > 4096) return fail(TRAJ_E_INVAL, "n_shapes must be in [1, 4096]");
+  Handle* h = new (std::nothrow) Handle();
+  if (h == nullptr) return fail(TRAJ_E_NOMEM, "host allocation failed");
+  h->p = p;
+  size_t off = 0;
+  for (int i = 0; i < n_shapes; ++i) {
+    const traj_shape& s = shapes[i];
+    if (s.n_time < traj::NC || s.n_time > traj::MAX_TIME || !(isfinite(s.t_f) && s.t_f > 0.f) || s.n_obs < 0 ||
+        s.n_obs > traj::MAX_OBS) {
+      delete h;
+      return fail(TRAJ_E_INVAL, "shape %d invalid (n_time in [%d, %d], t_f > 0, n_obs in [0, %d])", i, traj::NC,
+                  traj::MAX_TIME, traj::MAX_OBS);
+    }
+    ShapeDesc d;
+    d.n = s.n_time;
+    d.m = s.n_obs;
+    d.t_f = s.t_f;
+    d.table_off = (int)off;
+    d.table64_off = i * traj::TAB64_SIZE;
+    off += (size_t)((traj::tab_size(d.n) + 63) / 64 * 64);
+    h->shapes.push_back(d);
+    if (d.n > h->max_n) h->max_n = d.n;
+    if (d.m > h->max_m) h->max_m = d.m;
+  }
+  h->table_floats = off;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if ((e = hipMalloc(&h->d_shapes, sizeof(ShapeDesc) * n_shapes)) != hipSuccess ||
+      (e = hipMalloc(&h->d_tables, sizeof(float) * off)) != hipSuccess ||
+      (e = hipMalloc(&h->d_tables64, sizeof(double) * traj::TAB64_SIZE * n_shapes)) != hipSuccess) {
+    traj_destroy(h);
+    return fail(TRAJ_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  if ((e = hipMemcpyAsync(h->d_shapes, h->shapes.data(), sizeof(ShapeDesc) * n_shapes, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = traj::launch_setup(h->d_shapes, n_shapes, consts(p), h->d_tables, h->d_tables64, h->max_n, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    traj_destroy(h);
+    return hip_fail(e, "traj_setup");
+  }
+  *handle_out = h;
+  return TRAJ_OK;
+}
+
+int traj_destroy(void* handle) {
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return TRAJ_OK;
+  if (h->d_shapes) hipFree(h->d_shapes);
+  if (h->d_tables) hipFree(h->d_tables);
+  if (h->d_tables64) hipFree(h->d_tables64);
+  delete h;
+  return TRAJ_OK;
+}
+
+int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
+                     void* stream) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  int rc = check_batch(h, batch);
+  if (rc != TRAJ_OK) return rc;
+  if (state == nullptr) return fail(TRAJ_E_INVAL, "state is NULL");
+  if (iters < 0 || iters > 100000) return fail(TRAJ_E_INVAL, "iters must be in [0, 100000]");
+  if (!isfinite(tol)) return fail(TRAJ_E_INVAL, "tol must be finite");
+  if ((flags & ~TRAJ_INIT_FROM_STATE) != 0) return fail(TRAJ_E_INVAL, "unknown flags 0x%x", flags);
+  if (batch->n_goals == 0) return TRAJ_OK;
+  if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
+  traj::SolveArgs a;
+  a.goal_off = batch->goal_off;
+  a.obs_off = batch->obs_off;
+  a.shape_id = batch->shape_id;
+  a.ego = batch->ego;
+  a.obs = batch->obs;
+  a.goal = batch->goal;
+  a.c = state->c;
+  a.lam = state->lam;
+  a.resid = state->resid;
+  a.iters_out = state->iters;
+  a.shapes = h->d_shapes;
+  a.tables = h->d_tables;
+  a.tables64 = h->d_tables64;
+  a.n_shapes = (int)h->shapes.size();
+  a.n_scenes = batch->n_scenes;
+  a.n_goals = batch->n_goals;
+  a.iters = iters;
+  a.flags = (int)flags;
+  a.tol = tol;
+  a.k = consts(h->p);
+  hipError_t e = traj::launch_solve(a, h->max_n, h->max_m, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traj_solve_batch launch");
+  return TRAJ_OK;
+}
+
+int traj_score(void* handle, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
+               int32_t* best, void* stream) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  int rc = check_batch(h, batch);
+  if (rc != TRAJ_OK) return rc;
+  if (state == nullptr || mc == nullptr) return fail(TRAJ_E_INVAL, "state / metacost is NULL");
+  if (mc->kind != 0 && mc->kind != 1) return fail(TRAJ_E_INVAL, "metacost kind must be 0 or 1");
+  if (!isfinite(mc->w1) || !isfinite(mc->w2)) return fail(TRAJ_E_INVAL, "metacost weights must be finite");
+  if (batch->n_scenes == 0) return TRAJ_OK;
+  if (mc->v_ref == nullptr || (mc->kind == 1 && mc->y_rl == nullptr))
+    return fail(TRAJ_E_INVAL, "metacost reference arrays are NULL");
+  if (best == nullptr || (batch->n_goals > 0 && (cost == nullptr || state->c == nullptr)))
+    return fail(TRAJ_E_INVAL, "cost / best / state.c is NULL");
+  traj::ScoreArgs a;
+  a.goal_off = batch->goal_off;
+  a.shape_id = batch->shape_id;
+  a.c = state->c;
+  a.shapes = h->d_shapes;
+  a.tables = h->d_tables;
+  a.n_shapes = (int)h->shapes.size();
+  a.n_scenes = batch->n_scenes;
+  a.n_goals = batch->n_goals;
+  a.kind = mc->kind;
+  a.v_ref = mc->v_ref;
+  a.y_rl = mc->y_rl;
+  a.w1 = mc->w1;
+  a.w2 = mc->w2;
+  a.psi_max = h->p.psi_max;
+  a.cost = cost;
+  a.best = best;
+  hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traj_score launch");
+  return TRAJ_OK;
+}
+
+int traj_debug_table_size(void* handle, int shape) {
+  Handle* h = (Handle*)handle;
+  if (h == nullptr || shape < 0 || shape >= (int)h->shapes.size()) return fail(TRAJ_E_SHAPE, "bad handle or shape");
+  return traj::tab_size(h->shapes[shape].n);
+}
+
+int traj_debug_operators(void* handle, int shape, double* out_f64, float* out_f32, void* stream) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  if (shape < 0 || shape >= (int)h->shapes.size()) return fail(TRAJ_E_SHAPE, "shape %d not set up", shape);
+  const ShapeDesc& d = h->shapes[shape];
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (out_f64)
+    e = hipMemcpyAsync(out_f64, h->d_tables64 + d.table64_off, sizeof(double) * traj::SYS_COUNT * traj::KMAX * traj::KMAX,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && out_f32)
+    e = hipMemcpyAsync(out_f32, h->d_tables + d.table_off, sizeof(float) * traj::tab_size(d.n), hipMemcpyDeviceToHost,
+                       st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "traj_debug_operators");
+  return TRAJ_OK;
+}
+
+int traj_debug_reduce(const float* in, float* out, int r, void* stream) {
+  g_err.clear();
+  if (in == nullptr || out == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
+  if (r != 16 && r != 32) return fail(TRAJ_E_INVAL, "r must be 16 or 32");
+  hipError_t e = traj::launch_debug_reduce(in, out, r, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traj_debug_reduce");
+  return TRAJ_OK;
+}
+
+}  // extern "C"

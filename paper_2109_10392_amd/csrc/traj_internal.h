@@ -1,0 +1,113 @@
+// Internal layout shared by the HIP kernels and the C-ABI implementation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "traj.h"
+
+namespace traj {
+
+constexpr int NC = TRAJ_N_COEF;  // Bernstein coefficients per axis
+constexpr int NX = 4;            // boundary rows of x: x(0), x'(0), x''(0), x(t_f)
+constexpr int NY = 6;            // boundary rows of y: + y'(t_f), y''(t_f)
+constexpr int NP = 4;            // boundary rows of psi: psi(0), psi'(0), psi(t_f), psi'(t_f)
+constexpr int KMAX = NC + NY;    // largest KKT system (17)
+constexpr int MAX_TIME = 192;    // three 64-lane slots
+constexpr int MAX_OBS = 64;
+constexpr int WAVE = 64;
+constexpr int GOALS_PER_WG = 4;  // one goal per wave, four waves per workgroup
+
+// Per-shape FP32 table, offsets in floats from the shape's table_off.
+//   basis:  P[NC][n], Pd[NC][n], Pdd[NC][n]        (coefficient-major, time fastest)
+//   square: MGx, Mx, MGy, My, Mp                   (each NC x NC row-major)
+//           MGx = Mx (rho F_ax^T F_ax) = Mx (rho (m P^T P + P''^T P'' + P'^T P'))
+//   boundary: Mbx[NC][NX], Mby[NC][NY], Mbp[NC][NP], M0bx[NC][NX], M0by[NC][NY]
+enum SquareId { SQ_MGX = 0, SQ_MX, SQ_MGY, SQ_MY, SQ_MP, SQ_COUNT };
+
+__host__ __device__ inline int tab_basis(int n, int which) { return which * NC * n; }
+__host__ __device__ inline int tab_square(int n, int id) { return 3 * NC * n + id * NC * NC; }
+__host__ __device__ inline int tab_bnd(int n) { return 3 * NC * n + SQ_COUNT * NC * NC; }
+// boundary sub-blocks relative to tab_bnd
+constexpr int BND_MBX = 0;
+constexpr int BND_MBY = BND_MBX + NC * NX;
+constexpr int BND_MBP = BND_MBY + NC * NY;
+constexpr int BND_M0BX = BND_MBP + NC * NP;
+constexpr int BND_M0BY = BND_M0BX + NC * NX;
+constexpr int BND_SIZE = BND_M0BY + NC * NY;
+__host__ __device__ inline int tab_size(int n) { return tab_bnd(n) + BND_SIZE; }
+
+// FP64 table per shape: the 5 KKT inverses (KMAX x KMAX each, verification),
+// then the operators of the x/y step that stay in FP64 in the solver:
+//   MGx, Mx, MGy, My (NC x NC), Mbx (NC x NX), Mby (NC x NY).
+// The x/y step adds these constant terms to the iterate every iteration and the
+// multipliers integrate whatever they carry, so their FP32 rounding would act
+// as a systematic per-iteration perturbation of the fixed point.
+enum SysId { SYS_X = 0, SYS_Y, SYS_P, SYS_0X, SYS_0Y, SYS_COUNT };
+constexpr int T64_INV = 0;
+constexpr int T64_MGX = SYS_COUNT * KMAX * KMAX;
+constexpr int T64_MX = T64_MGX + NC * NC;
+constexpr int T64_MGY = T64_MX + NC * NC;
+constexpr int T64_MY = T64_MGY + NC * NC;
+constexpr int T64_MBX = T64_MY + NC * NC;
+constexpr int T64_MBY = T64_MBX + NC * NX;
+constexpr int TAB64_SIZE = T64_MBY + NC * NY;
+
+struct ShapeDesc {
+  int n;          // samples
+  int m;          // obstacles
+  float t_f;
+  int table_off;  // float offset of the FP32 table
+  int table64_off;
+};
+
+struct SolverConst {
+  float rho, a, b, v_min, v_max, a_max, psi_max;
+};
+
+struct SolveArgs {
+  const int32_t* goal_off;
+  const int32_t* obs_off;
+  const int32_t* shape_id;
+  const float* ego;
+  const float* obs;
+  const float* goal;
+  float* c;
+  float* lam;
+  float* resid;
+  int32_t* iters_out;
+  const ShapeDesc* shapes;
+  const float* tables;
+  const double* tables64;
+  int n_shapes;
+  int n_scenes;
+  int n_goals;
+  int iters;
+  int flags;
+  float tol;
+  SolverConst k;
+};
+
+struct ScoreArgs {
+  const int32_t* goal_off;
+  const int32_t* shape_id;
+  const float* c;
+  const ShapeDesc* shapes;
+  const float* tables;
+  int n_shapes;
+  int n_scenes;
+  int n_goals;
+  int kind;
+  const float* v_ref;
+  const float* y_rl;
+  float w1, w2, psi_max;
+  float* cost;
+  int32_t* best;
+};
+
+// Launchers (defined next to their kernels). Return hipSuccess or the launch error.
+hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverConst& k, float* d_tables,
+                        double* d_tables64, int max_n, hipStream_t stream);
+hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t stream);
+hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
+
+}  // namespace traj

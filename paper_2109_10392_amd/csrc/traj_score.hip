@@ -1,0 +1,141 @@
+// Meta-cost ranking (Sec. III-F): eq. 25 (cruise) or eq. 26 (high speed close
+// to the right lane) per goal, the heading post-filter of Sec. III (assumption
+// 2: discard |psi| beyond psi_max), then the lowest-index argmin per scene.
+#include "traj_internal.h"
+
+namespace traj {
+namespace {
+
+constexpr int SCORE_THREADS = WAVE * GOALS_PER_WG;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, WAVE));
+  return v;
+}
+
+// scene of a goal: largest s with goal_off[s] <= g
+__device__ int scene_of(const int32_t* goal_off, int n_scenes, int g) {
+  int lo = 0, hi = n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (goal_off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// One wave per goal, lanes over time samples.
+__global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int g = blockIdx.x * GOALS_PER_WG + (threadIdx.x >> 6);
+  if (g >= A.n_goals) return;
+  const int s = scene_of(A.goal_off, A.n_scenes, g);
+  const int sid = A.shape_id[s];
+  if (sid < 0 || sid >= A.n_shapes) {
+    if (lane == 0) A.cost[g] = __builtin_nanf("");
+    return;
+  }
+  const ShapeDesc sd = A.shapes[sid];
+  const float* T = A.tables + sd.table_off;
+  const int n = sd.n, NG = A.n_goals;
+  float cx[NC], cy[NC], cp[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    cx[k] = A.c[(0 * NC + k) * NG + g];
+    cy[k] = A.c[(1 * NC + k) * NG + g];
+    cp[k] = A.c[(2 * NC + k) * NG + g];
+  }
+  const float vref = A.v_ref[s];
+  const float yrl = (A.kind == 1 && A.y_rl != nullptr) ? A.y_rl[s] : 0.f;
+  float acc = 0.f, pmax = 0.f;
+  for (int t = lane; t < n; t += WAVE) {
+    float xd = 0.f, yd = 0.f, y = 0.f, psi = 0.f;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const float p = T[tab_basis(n, 0) + k * n + t];
+      const float pd = T[tab_basis(n, 1) + k * n + t];
+      xd = fmaf(pd, cx[k], xd);
+      yd = fmaf(pd, cy[k], yd);
+      y = fmaf(p, cy[k], y);
+      psi = fmaf(p, cp[k], psi);
+    }
+    const float v = sqrtf(fmaf(xd, xd, yd * yd));
+    const float dv = v - vref;
+    if (A.kind == 0) {
+      acc = fmaf(dv, dv, acc);
+    } else {
+      const float dy = y - yrl;
+      acc = fmaf(A.w1 * dv, dv, fmaf(A.w2 * dy, dy, acc));
+    }
+    pmax = fmaxf(pmax, fabsf(psi));
+  }
+  acc = wave_sum(acc);
+  pmax = wave_max(pmax);
+  if (lane == 0) A.cost[g] = (pmax > A.psi_max) ? __builtin_inff() : acc;
+}
+
+// One workgroup per scene: lowest index attaining the minimum finite cost.
+__global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
+  __shared__ float sv[SCORE_THREADS / WAVE];
+  __shared__ int si[SCORE_THREADS / WAVE];
+  const int s = blockIdx.x;
+  const int g0 = A.goal_off[s], g1 = min((int)A.goal_off[s + 1], A.n_goals);
+  float best = __builtin_inff();
+  int bi = 0x7fffffff;
+  for (int g = g0 + (int)threadIdx.x; g < g1; g += SCORE_THREADS) {
+    const float c = A.cost[g];
+    if (isfinite(c) && (c < best || (c == best && g - g0 < bi))) {
+      best = c;
+      bi = g - g0;
+    }
+  }
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    const float ov = __shfl_xor(best, d, WAVE);
+    const int oi = __shfl_xor(bi, d, WAVE);
+    if (ov < best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    sv[wv] = best;
+    si[wv] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < SCORE_THREADS / WAVE; ++w) {
+      if (sv[w] < best || (sv[w] == best && si[w] < bi)) {
+        best = sv[w];
+        bi = si[w];
+      }
+    }
+    A.best[s] = (bi == 0x7fffffff) ? -1 : bi;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream) {
+  (void)max_n;
+  if (a.n_goals > 0) {
+    const int blocks = (a.n_goals + GOALS_PER_WG - 1) / GOALS_PER_WG;
+    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(SCORE_THREADS), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.n_scenes > 0) hipLaunchKernelGGL(k_argmin, dim3(a.n_scenes), dim3(SCORE_THREADS), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace traj

@@ -1,0 +1,611 @@
+// Batched alternating minimisation (Algorithm 1, Sec. III-D) on gfx950.
+//
+// Mapping: one wavefront per goal, lanes over time samples (lane l holds samples
+// l, l+64, ...: S "slots"), four goals (waves) of one scene per workgroup so the
+// scene's obstacle predictions are staged once in LDS. Each goal's iterate
+// stays in registers for all iterations; nothing goes back to HBM until the end.
+//
+// Per iteration, with c the coefficients of the previous x/y step:
+//   x/y step (eq. 12 via eqs. 17-18). F^T g splits into a part linear in c and
+//   the projection corrections, because the obstacle rows of g are
+//   x + dx (d/du - 1), the acceleration rows x'' + s_a and the velocity rows
+//   x' + (z - x'), with M, M_b blocks of the KKT inverse. The dense stacked F of
+//   eq. 9 is never formed.
+//   heading step (eq. 13 via eqs. 19-20): theta = atan2(y', x'),
+//     c_psi = M_psi (rho P^T theta + lam_psi) + M_bpsi b_psi.
+//   velocity (eq. 21), obstacle polar variables (eq. 22 and the 1-D minimiser of
+//   eq. 15 clipped to d >= 1: d/du - 1 = max(0, 1/du - 1), du = |(dx/a, dy/b)|),
+//   acceleration polar variables (eq. 16: d_a = min(a_max, |(x'', y'')|)).
+//   multipliers (eq. 23): lam += rho F_ax^T (g - F_ax c) = rho u~ with
+//   u~ = P^T s_o + P''^T s_a + P'^T (z - x'); (eq. 24, residual oriented as in
+//   eq. 23): lam_psi += rho P^T (theta - psi). Both increments are contracted
+//   from per-sample residuals, never as a difference of two large products
+//   (P^T theta - P^T P c_psi): the multipliers integrate every iteration's
+//   rounding, and the difference form makes FP32 drift well past 1e-4.
+//   Correspondingly rho F^T g = (rho F_ax^T F_ax) c + rho u~, so the x/y step
+//   is c_new = (M rho F_ax^T F_ax) c + M (rho u~ + lam) + M_b b.
+// The contractions over time (P^T s, P^T theta) are lane-parallel products
+// followed by a reduce-scatter across the wave (permlane swaps + DPP); the
+// 11x11 applies run one output row per lane with the input broadcast through
+// scalar registers.
+#include "traj_internal.h"
+
+namespace traj {
+namespace {
+
+constexpr int SOLVE_THREADS = WAVE * GOALS_PER_WG;
+
+constexpr int DPP_QUAD_1032 = 0xB1;  // quad_perm [1,0,3,2]: partner lane ^ 1
+constexpr int DPP_QUAD_2301 = 0x4E;  // quad_perm [2,3,0,1]: partner lane ^ 2
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane p <-> 15 - p within a row of 16
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane p <-> 7 - p within a half-row of 8
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// lanes 0-31 of the result: a summed over lane pairs (l, l+32); lanes 32-63: b summed likewise
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  // copy the two results out as values first: a bit_cast of the vector element
+  // lvalue r[1] is lowered as element 0 by this compiler
+  const unsigned r0 = r[0], r1 = r[1];
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
+// within each 32-lane half: lanes 0-15 a summed over (l, l+16), lanes 16-31 b summed likewise
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  const unsigned r0 = r[0], r1 = r[1];
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
+// lanes 32-63 receive lanes 0-31 of v (lanes 0-31 keep v)
+__device__ __forceinline__ float permlane_lo_to_hi(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned r0 = r[0];
+  return __builtin_bit_cast(float, r0);
+}
+
+// Wave-wide sums of 32 per-lane values: on return lane l holds the sum of value l >> 1.
+__device__ __forceinline__ float reduce32(const float (&v)[32]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  float s[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s[i] = swap32_add(v[i], v[i + 16]);
+  float t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = swap16_add(s[i], s[i + 8]);
+  const bool lo8 = (lane & 8) == 0;
+  float u[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = (lo8 ? t[i] : t[i + 4]) + dpp<DPP_ROW_MIRROR>(lo8 ? t[i + 4] : t[i]);
+  const bool lo4 = (lane & 4) == 0;
+  float w[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) w[i] = (lo4 ? u[i] : u[i + 2]) + dpp<DPP_ROW_HALF_MIRROR>(lo4 ? u[i + 2] : u[i]);
+  const bool lo2 = (lane & 2) == 0;
+  float z = (lo2 ? w[0] : w[1]) + dpp<DPP_QUAD_2301>(lo2 ? w[1] : w[0]);
+  return z + dpp<DPP_QUAD_1032>(z);
+}
+
+// Wave-wide sums of 16 per-lane values: on return lane l holds the sum of value l >> 2.
+__device__ __forceinline__ float reduce16(const float (&v)[16]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  float s[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s[i] = swap32_add(v[i], v[i + 8]);
+  float t[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[i] = swap16_add(s[i], s[i + 4]);
+  const bool lo8 = (lane & 8) == 0;
+  float u[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) u[i] = (lo8 ? t[i] : t[i + 2]) + dpp<DPP_ROW_MIRROR>(lo8 ? t[i + 2] : t[i]);
+  const bool lo4 = (lane & 4) == 0;
+  float z = (lo4 ? u[0] : u[1]) + dpp<DPP_ROW_HALF_MIRROR>(lo4 ? u[1] : u[0]);
+  z += dpp<DPP_QUAD_2301>(z);
+  return z + dpp<DPP_QUAD_1032>(z);
+}
+
+// Value slots of the two 32-way reductions (value v lands in lanes 2v, 2v+1).
+// After the projections:
+constexpr int R_UX = 0;     // u~_x[0..10]  -> lanes 2k
+constexpr int R_OBS = 11;   // r_obs^2      -> lane 22
+constexpr int R_ACC = 12;   // r_acc^2      -> lane 24
+constexpr int R_NH = 13;    // r_nh^2       -> lane 26
+constexpr int R_PSI = 14;   // r_psi^2      -> lane 28
+constexpr int R_UY = 16;    // u~_y[0..10]  -> lanes 32 + 2k
+// After the heading input:
+constexpr int H_W = 0;      // P^T theta            -> lanes 2k
+constexpr int H_E = 16;     // P^T (theta - psi) of the previous heading step -> lanes 32 + 2k
+
+struct Goal {
+  int n, m;
+  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2;
+};
+
+// Basis rows of the lane's samples (slot s holds sample lane + 64 s).
+template <int S>
+struct Lane {
+  float P[S][NC], Pd[S][NC], Pdd[S][NC];
+  bool val[S];
+};
+
+__device__ __forceinline__ float dotc(const float (&r)[NC], const float (&c)[NC]) {
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc = fmaf(r[k], c[k], acc);
+  return acc;
+}
+
+// Heading surrogate input (eq. 13): x', y', theta = atan2(y', x') per slot and the
+// lane's share of P^T theta, plus P^T e_psi for the pending heading multiplier.
+template <int S>
+__device__ __forceinline__ void heading_input(const Lane<S>& L, const float (&cx)[NC], const float (&cy)[NC],
+                                              const float (&ep)[S], float (&xd)[S], float (&yd)[S],
+                                              float (&th)[S], float (&part)[32]) {
+#pragma unroll
+  for (int k = 0; k < 32; ++k) part[k] = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    xd[s] = dotc(L.Pd[s], cx);
+    yd[s] = dotc(L.Pd[s], cy);
+    th[s] = atan2f(yd[s], xd[s]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      part[H_W + k] = fmaf(L.P[s][k], th[s], part[H_W + k]);
+      part[H_E + k] = fmaf(L.P[s][k], ep[s], part[H_E + k]);
+    }
+  }
+}
+
+// Projections (eqs. 21, 22, 15, 16) at the current coefficients. Produces the
+// lane's share of
+//   u~ = P^T s_o + P''^T s_a + P'^T (z - x')   (per axis)
+// where s_o, s_a are the obstacle and acceleration corrections g - F c of those
+// rows and z = v (cos psi, sin psi): u~ = F_ax^T (g - F_ax c), the multiplier
+// increment of eq. 23 divided by rho, formed from per-sample residuals. Also the
+// squared residual components, and e_psi = theta - psi per slot for eq. 24.
+template <int S>
+__device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float2* __restrict__ xi,
+                                            const float (&cx)[NC], const float (&cy)[NC], const float (&cp)[NC],
+                                            const float (&xd)[S], const float (&yd)[S], const float (&th)[S],
+                                            float (&ep)[S], float (&part)[32]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int k = 0; k < 32; ++k) part[k] = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const float x = dotc(L.P[s], cx), y = dotc(L.P[s], cy);
+    const float xdd = dotc(L.Pdd[s], cx), ydd = dotc(L.Pdd[s], cy);
+    const float psi = dotc(L.P[s], cp);
+    // velocity, eq. 21
+    const float v = fminf(fmaxf(sqrtf(fmaf(xd[s], xd[s], yd[s] * yd[s])), G.vmin), G.vmax);
+    float sn, cs;
+    sincosf(psi, &sn, &cs);
+    const float ex = fmaf(v, cs, -xd[s]), ey = fmaf(v, sn, -yd[s]);  // z - x'
+    // acceleration polar variables, eq. 16: d_a = min(a_max, h), s_a = (x'', y'') (d_a / h - 1)
+    const float h2 = fmaf(xdd, xdd, ydd * ydd);
+    const float fa = h2 > G.amax2 ? G.amax * rsqrtf(h2) - 1.f : 0.f;
+    const float sax = xdd * fa, say = ydd * fa;
+    // obstacle polar variables, eqs. 15 and 22, in units scaled by (1/a, 1/b):
+    // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse
+    const float X = x * G.inv_a, Y = y * G.inv_b;
+    const int t = L.val[s] ? lane + WAVE * s : 0;
+    const float2* q = xi + t;
+    float Sx = 0.f, Sy = 0.f, ro = 0.f;
+    int j = 0;
+    for (; j + 4 <= G.m; j += 4) {
+      float tx[4], ty[4], qq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float2 o = q[(j + u) * G.n];
+        tx[u] = X - o.x;
+        ty[u] = Y - o.y;
+        qq[u] = fmaf(tx[u], tx[u], ty[u] * ty[u]);
+      }
+      if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (qq[u] < 1.f) {
+            if (qq[u] > 0.f) {
+              const float f = rsqrtf(qq[u]) - 1.f;
+              Sx = fmaf(tx[u], f, Sx);
+              Sy = fmaf(ty[u], f, Sy);
+              ro = fmaf(fmaf(G.a2 * tx[u], tx[u], G.b2 * ty[u] * ty[u]), f * f, ro);
+            } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
+              Sx += 1.f;
+              ro += G.a2;
+            }
+          }
+        }
+      }
+    }
+    for (; j < G.m; ++j) {
+      const float2 o = q[j * G.n];
+      const float tx = X - o.x, ty = Y - o.y;
+      const float qq = fmaf(tx, tx, ty * ty);
+      if (qq < 1.f) {
+        if (qq > 0.f) {
+          const float f = rsqrtf(qq) - 1.f;
+          Sx = fmaf(tx, f, Sx);
+          Sy = fmaf(ty, f, Sy);
+          ro = fmaf(fmaf(G.a2 * tx, tx, G.b2 * ty * ty), f * f, ro);
+        } else {
+          Sx += 1.f;
+          ro += G.a2;
+        }
+      }
+    }
+    const float sox = G.a * Sx, soy = G.b * Sy;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      part[R_UX + k] = fmaf(L.P[s][k], sox, fmaf(L.Pdd[s][k], sax, fmaf(L.Pd[s][k], ex, part[R_UX + k])));
+      part[R_UY + k] = fmaf(L.P[s][k], soy, fmaf(L.Pdd[s][k], say, fmaf(L.Pd[s][k], ey, part[R_UY + k])));
+    }
+    ep[s] = L.val[s] ? th[s] - psi : 0.f;
+    if (L.val[s]) {
+      part[R_OBS] += ro;
+      part[R_ACC] += fmaf(sax, sax, say * say);
+      part[R_NH] += fmaf(ex, ex, ey * ey);
+      part[R_PSI] += ep[s] * ep[s];
+    }
+  }
+}
+
+template <int S>
+__device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float* __restrict__ T,
+                           const float2* __restrict__ xi, int scene, int g) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int NG = A.n_goals;
+  Goal G;
+  G.n = sd.n;
+  G.m = sd.m;
+  G.rho = A.k.rho;
+  G.a = A.k.a;
+  G.b = A.k.b;
+  G.inv_a = 1.f / G.a;
+  G.inv_b = 1.f / G.b;
+  G.a2 = G.a * G.a;
+  G.b2 = G.b * G.b;
+  G.vmin = A.k.v_min;
+  G.vmax = A.k.v_max;
+  G.amax = A.k.a_max;
+  G.amax2 = G.amax * G.amax;
+  const float rho = G.rho;
+  const int n = G.n;
+
+  Lane<S> L;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int t = lane + WAVE * s;
+    L.val[s] = t < n;
+    const int tc = L.val[s] ? t : 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      L.P[s][k] = L.val[s] ? T[tab_basis(n, 0) + k * n + tc] : 0.f;
+      L.Pd[s][k] = L.val[s] ? T[tab_basis(n, 1) + k * n + tc] : 0.f;
+      L.Pdd[s][k] = L.val[s] ? T[tab_basis(n, 2) + k * n + tc] : 0.f;
+    }
+  }
+  // Home lanes: coefficient k of x lives in lanes 2k, 2k+1; of y and psi in 32+2k, 33+2k.
+  // Every lane computes the rows of its index k for all three applies.
+  const int k_home = min((lane & 31) >> 1, NC - 1);
+  const bool upper = lane >= 32;
+  // x/y step operators in FP64, heading step operator in FP32
+  const double* T64 = A.tables64 + sd.table64_off;
+  double rMGx[NC], rMx[NC], rMGy[NC], rMy[NC];
+  float rMp[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    rMGx[j] = T64[T64_MGX + k_home * NC + j];
+    rMx[j] = T64[T64_MX + k_home * NC + j];
+    rMGy[j] = T64[T64_MGY + k_home * NC + j];
+    rMy[j] = T64[T64_MY + k_home * NC + j];
+    rMp[j] = T[tab_square(n, SQ_MP) + k_home * NC + j];
+  }
+  // boundary values (eq. 8b) and the particular parts M_b b of each step
+  const float* e = A.ego + 8 * scene;
+  const float* gl = A.goal + 2 * g;
+  const float bx[NX] = {e[0], e[2], e[4], gl[0]};
+  const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
+  const float bp[NP] = {e[6], e[7], 0.f, 0.f};
+  const float* Bt = T + tab_bnd(n);
+  double c0x = 0.0, c0y = 0.0;
+  float c0p = 0.f;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) c0x = fma(T64[T64_MBX + k_home * NX + j], (double)bx[j], c0x);
+#pragma unroll
+  for (int j = 0; j < NY; ++j) c0y = fma(T64[T64_MBY + k_home * NY + j], (double)by[j], c0y);
+#pragma unroll
+  for (int j = 0; j < NP; ++j) c0p = fmaf(Bt[BND_MBP + k_home * NP + j], bp[j], c0p);
+
+  float cx[NC], cy[NC], cp[NC];
+  // multipliers at their home lanes: lxy = lambda_x[k] (lower half) / lambda_y[k] (upper
+  // half); lp = lambda_psi[k] (upper half)
+  float lxy, lp;
+  const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
+  if (cold) {
+    // boundary-only minimum-acceleration start, lambda = 0
+    float vx = 0.f, vy = 0.f;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) vx = fmaf(Bt[BND_M0BX + k_home * NX + j], bx[j], vx);
+#pragma unroll
+    for (int j = 0; j < NY; ++j) vy = fmaf(Bt[BND_M0BY + k_home * NY + j], by[j], vy);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      cx[j] = rdlane(vx, 2 * j);
+      cy[j] = rdlane(vy, 2 * j);
+      cp[j] = 0.f;
+    }
+    lxy = 0.f;
+    lp = 0.f;
+  } else {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      cx[j] = A.c[(0 * NC + j) * NG + g];
+      cy[j] = A.c[(1 * NC + j) * NG + g];
+      cp[j] = A.c[(2 * NC + j) * NG + g];
+    }
+    lxy = A.lam[((upper ? 1 : 0) * NC + k_home) * NG + g];
+    lp = A.lam[(2 * NC + k_home) * NG + g];
+  }
+
+  float uxy;  // u~_x[k] at lanes 2k, u~_y[k] at lanes 32+2k, residuals at lanes 22..28
+  float part[32];
+  float ep[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) ep[s] = 0.f;
+  {
+    // split variables of the starting point: heading QP (cold start only), v, (alpha, d),
+    // (alpha_a, d_a). No multiplier is updated here.
+    float xd[S], yd[S], th[S];
+    heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
+    if (cold) {
+      const float wE = reduce32(part);
+      const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
+      const float rp = fmaf(rho, w, lp);
+      float np = c0p;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) np = fmaf(rMp[j], rdlane(rp, 32 + 2 * j), np);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
+    }
+    projections<S>(G, L, xi, cx, cy, cp, xd, yd, th, ep, part);
+    uxy = reduce32(part);
+#pragma unroll
+    for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
+  }
+
+  int done = 0;
+  for (int it = 0; it < A.iters; ++it) {
+    // ---- x/y step (eq. 12 through eq. 18):
+    // c_new = M (rho F^T g + lambda) + M_b b = (M rho F_ax^T F_ax) c + M (rho u~ + lambda) + M_b b
+    {
+      const float r = fmaf(rho, uxy, lxy);
+      float rx[NC], ry[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        rx[j] = rdlane(r, 2 * j);
+        ry[j] = rdlane(r, 32 + 2 * j);
+      }
+      double nx = c0x, ny = c0y;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        nx = fma(rMGx[j], (double)cx[j], fma(rMx[j], (double)rx[j], nx));
+        ny = fma(rMGy[j], (double)cy[j], fma(rMy[j], (double)ry[j], ny));
+      }
+      const float fx = (float)nx, fy = (float)ny;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        cx[j] = rdlane(fx, 2 * j);
+        cy[j] = rdlane(fy, 2 * j);
+      }
+    }
+    // ---- pending heading multiplier (eq. 24 of the previous step) and heading step
+    // (eq. 13 through eq. 20)
+    float xd[S], yd[S], th[S];
+    {
+      heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
+      const float wE = reduce32(part);
+      lp = fmaf(rho, wE, lp);                 // upper lanes: lambda_psi += rho P^T (theta - psi)
+      const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
+      const float rp = fmaf(rho, w, lp);
+      float np = c0p;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) np = fmaf(rMp[j], rdlane(rp, 32 + 2 * j), np);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
+    }
+    // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
+    projections<S>(G, L, xi, cx, cy, cp, xd, yd, th, ep, part);
+    uxy = reduce32(part);
+    // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
+    lxy = fmaf(rho, uxy, lxy);
+    done = it + 1;
+    if (A.tol > 0.f && done % 5 == 0) {
+      const float worst = fmaxf(fmaxf(rdlane(uxy, 2 * R_OBS), rdlane(uxy, 2 * R_ACC)), rdlane(uxy, 2 * R_NH));
+      if (sqrtf(worst) <= A.tol) break;
+    }
+  }
+  if (done > 0) {
+    // the heading multiplier step of the last iteration
+#pragma unroll
+    for (int k = 0; k < 32; ++k) part[k] = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) part[H_E + k] = fmaf(L.P[s][k], ep[s], part[H_E + k]);
+    }
+    lp = fmaf(rho, reduce32(part), lp);
+  }
+
+  // ---- write back from the home lanes
+  const int k = (lane & 31) >> 1;
+  if ((lane & 1) == 0 && k < NC) {
+    float vx = 0.f, vy = 0.f, vp = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (j == k) {
+        vx = cx[j];
+        vy = cy[j];
+        vp = cp[j];
+      }
+    }
+    if (!upper) {
+      A.c[(0 * NC + k) * NG + g] = vx;
+      A.lam[(0 * NC + k) * NG + g] = lxy;
+    } else {
+      A.c[(1 * NC + k) * NG + g] = vy;
+      A.lam[(1 * NC + k) * NG + g] = lxy;
+      A.c[(2 * NC + k) * NG + g] = vp;
+      A.lam[(2 * NC + k) * NG + g] = lp;
+    }
+  }
+  if (A.resid != nullptr) {
+    // residuals of the returned iterate (of the starting point when iters == 0)
+    const float r_obs = rdlane(uxy, 2 * R_OBS), r_acc = rdlane(uxy, 2 * R_ACC);
+    const float r_nh = rdlane(uxy, 2 * R_NH), r_psi = rdlane(uxy, 2 * R_PSI);
+    if (lane < 4) {
+      const float rr = lane == 0 ? r_obs : (lane == 1 ? r_acc : (lane == 2 ? r_nh : r_psi));
+      A.resid[lane * NG + g] = sqrtf(rr);
+    }
+  }
+  if (A.iters_out != nullptr && lane == 0) A.iters_out[g] = done;
+}
+
+// Workgroup -> (scene, first goal): scene s owns ceil(goals_s / GOALS_PER_WG)
+// consecutive workgroups. Returns scene -1 past the last one.
+__device__ void locate(const int32_t* goal_off, int n_scenes, int* sh, int* scan) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1), wv = tid >> 6;
+  if (tid == 0) {
+    sh[0] = -1;
+    sh[1] = 0;
+  }
+  int base = 0;
+  for (int c0 = 0; c0 < n_scenes; c0 += SOLVE_THREADS) {
+    const int s = c0 + tid;
+    const int cnt = (s < n_scenes) ? (goal_off[s + 1] - goal_off[s] + GOALS_PER_WG - 1) / GOALS_PER_WG : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const int y = __shfl_up(incl, d, WAVE);
+      if (lane >= d) incl += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) scan[wv] = incl;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < GOALS_PER_WG; ++w) {
+      if (w < wv) pre += scan[w];
+      tot += scan[w];
+    }
+    incl += pre;
+    const int excl = incl - cnt;
+    const int b = (int)blockIdx.x - base;
+    if (cnt > 0 && b >= excl && b < incl) {
+      sh[0] = s;
+      sh[1] = goal_off[s] + GOALS_PER_WG * (b - excl);
+    }
+    base += tot;
+    if (base > (int)blockIdx.x) break;  // uniform: every thread sees the same base
+  }
+  __syncthreads();
+}
+
+template <int S>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
+  extern __shared__ float2 xi[];  // [m][n] obstacle predictions, scaled by (1/a, 1/b)
+  __shared__ int sh[2];
+  __shared__ int scan[GOALS_PER_WG];
+  locate(A.goal_off, A.n_scenes, sh, scan);
+  const int scene = sh[0];
+  if (scene < 0) return;
+  const int g0 = sh[1];
+  const int g1 = min(min(g0 + GOALS_PER_WG, (int)A.goal_off[scene + 1]), A.n_goals);
+  const int sid = A.shape_id[scene];
+  const int o0 = A.obs_off[scene];
+  const int m_scene = A.obs_off[scene + 1] - o0;
+  bool bad = sid < 0 || sid >= A.n_shapes;
+  ShapeDesc sd = {};
+  if (!bad) sd = A.shapes[sid];
+  bad = bad || m_scene != sd.m || sd.n > WAVE * S || sd.n < NC;
+  const int tid = threadIdx.x;
+  const int g = g0 + (tid >> 6);
+  if (bad) {
+    if (A.resid != nullptr && g < g1 && (tid & 63) < 4) A.resid[(tid & 63) * A.n_goals + g] = __builtin_nanf("");
+    if (A.iters_out != nullptr && g < g1 && (tid & 63) == 0) A.iters_out[g] = 0;
+    return;
+  }
+  const int n = sd.n, m = sd.m;
+  const float dt = sd.t_f / (float)(n - 1);
+  const float inv_a = 1.f / A.k.a, inv_b = 1.f / A.k.b;
+  for (int e = tid; e < m * n; e += SOLVE_THREADS) {
+    const int j = e / n, i = e - j * n;
+    const float* o = A.obs + 4 * (o0 + j);
+    const float t = (float)i * dt;
+    xi[e] = make_float2(fmaf(o[2], t, o[0]) * inv_a, fmaf(o[3], t, o[1]) * inv_b);
+  }
+  __syncthreads();
+  if (g >= g1) return;
+  solve_goal<S>(A, sd, A.tables + sd.table_off, xi, scene, g);
+}
+
+// Lane-layout check of the two reductions: in[R][64] -> out[64].
+__global__ void k_debug_reduce(const float* in, float* out, int r) {
+  const int lane = threadIdx.x;
+  if (r == 32) {
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = in[i * WAVE + lane];
+    out[lane] = reduce32(v);
+  } else {
+    float v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = in[i * WAVE + lane];
+    out[lane] = reduce16(v);
+  }
+}
+
+template <int S>
+hipError_t set_smem(size_t smem) {
+  if (smem <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_am<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+}
+
+}  // namespace
+
+hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream) {
+  hipLaunchKernelGGL(k_debug_reduce, dim3(1), dim3(WAVE), 0, stream, in, out, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t stream) {
+  if (a.n_goals <= 0) return hipSuccess;
+  const int blocks = (a.n_goals + GOALS_PER_WG - 1) / GOALS_PER_WG + a.n_scenes;
+  const size_t smem = sizeof(float2) * (size_t)max_n * (size_t)(max_m > 0 ? max_m : 1);
+  const int S = (max_n + WAVE - 1) / WAVE;
+  if (smem > 160 * 1024) return hipErrorInvalidValue;
+  const hipError_t e = (S <= 1) ? set_smem<1>(smem) : (S == 2 ? set_smem<2>(smem) : set_smem<3>(smem));
+  if (e != hipSuccess) return e;
+  if (S <= 1)
+    hipLaunchKernelGGL(k_am<1>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
+  else if (S == 2)
+    hipLaunchKernelGGL(k_am<2>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
+  else
+    hipLaunchKernelGGL(k_am<3>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace traj

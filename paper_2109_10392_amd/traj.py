@@ -1,0 +1,213 @@
+"""Python binding of libtraj (ctypes): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module moves pointers,
+sizes and the current HIP stream across the C-ABI declared in include/traj.h.
+PyTorch supplies device memory and the stream. There is no fallback: if
+libtraj.so is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtraj.so")
+
+TRAJ_OK = 0
+TRAJ_INIT_COLD = 0x0
+TRAJ_INIT_FROM_STATE = 0x1
+N_COEF = 11
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_coef", ctypes.c_int32), ("rho", ctypes.c_float), ("a", ctypes.c_float),
+                ("b", ctypes.c_float), ("v_min", ctypes.c_float), ("v_max", ctypes.c_float),
+                ("a_max", ctypes.c_float), ("psi_max", ctypes.c_float)]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("n_time", ctypes.c_int32), ("t_f", ctypes.c_float), ("n_obs", ctypes.c_int32)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("n_scenes", ctypes.c_int32), ("n_goals", ctypes.c_int32),
+                ("goal_off", ctypes.c_void_p), ("obs_off", ctypes.c_void_p), ("shape_id", ctypes.c_void_p),
+                ("ego", ctypes.c_void_p), ("obs", ctypes.c_void_p), ("goal", ctypes.c_void_p)]
+
+
+class StateC(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("resid", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p)]
+
+
+class MetaC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("v_ref", ctypes.c_void_p), ("w1", ctypes.c_float),
+                ("w2", ctypes.c_float), ("y_rl", ctypes.c_void_p)]
+
+
+EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
+           "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce")
+
+_lib = None
+
+
+def lib():
+    """Load libtraj.so once; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2109_10392_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+    L.traj_setup.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Shape), i32, vp, ctypes.POINTER(vp)]
+    L.traj_solve_batch.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), i32, f32, ctypes.c_uint32, vp]
+    L.traj_score.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), ctypes.POINTER(MetaC), vp, vp, vp]
+    L.traj_destroy.argtypes = [vp]
+    L.traj_last_error.restype = ctypes.c_char_p
+    L.traj_debug_operators.argtypes = [vp, i32, vp, vp, vp]
+    L.traj_debug_table_size.argtypes = [vp, i32]
+    L.traj_debug_reduce.argtypes = [vp, vp, i32, vp]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_char_p if name == "traj_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+class TrajError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libtraj error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != TRAJ_OK:
+        raise TrajError(rc, lib().traj_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(p: dict) -> Params:
+    return Params(int(p["n_coef"]), float(p["rho"]), float(p["a"]), float(p["b"]), float(p["v_min"]),
+                  float(p["v_max"]), float(p["a_max"]), float(p["psi_max"]))
+
+
+@dataclass
+class DeviceBatch:
+    """Device copy of a scenes.Batch (or any arrays of the same layout)."""
+    n_scenes: int
+    n_goals: int
+    goal_off: object
+    obs_off: object
+    shape_id: object
+    ego: object
+    obs: object
+    goal: object
+    shapes: list
+
+    @staticmethod
+    def from_batch(batch, device="cuda", shapes=None):
+        import torch
+        shapes = list(shapes) if shapes is not None else batch.shapes()
+        sid = np.array([shapes.index((s.n_time, float(s.t_f), int(s.obs.shape[0]))) for s in batch.scenes], np.int32)
+
+        def t(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+
+        obs = batch.obs()
+        if obs.shape[0] == 0:
+            obs = np.zeros((1, 4), np.float32)
+        return DeviceBatch(batch.n_scenes, batch.n_goals, t(batch.goal_off(), torch.int32),
+                           t(batch.obs_off(), torch.int32), t(sid, torch.int32), t(batch.ego(), torch.float32),
+                           t(obs, torch.float32), t(batch.goals(), torch.float32), shapes)
+
+    def c_struct(self) -> BatchC:
+        return BatchC(self.n_scenes, self.n_goals, _ptr(self.goal_off), _ptr(self.obs_off), _ptr(self.shape_id),
+                      _ptr(self.ego), _ptr(self.obs), _ptr(self.goal))
+
+
+@dataclass
+class DeviceState:
+    c: object      # [3, 11, G] float32
+    lam: object    # [3, 11, G] float32
+    resid: object  # [4, G] float32
+    iters: object  # [G] int32
+
+    @staticmethod
+    def empty(n_goals, device="cuda"):
+        import torch
+        z = lambda *s: torch.zeros(*s, device=device, dtype=torch.float32)
+        return DeviceState(z(3, N_COEF, n_goals), z(3, N_COEF, n_goals), z(4, n_goals),
+                           torch.zeros(n_goals, device=device, dtype=torch.int32))
+
+    def c_struct(self) -> StateC:
+        return StateC(_ptr(self.c), _ptr(self.lam), _ptr(self.resid), _ptr(self.iters))
+
+
+class Solver:
+    """Owns a libtraj handle set up for a list of (n_time, t_f, n_obs) shapes."""
+
+    def __init__(self, params: dict, shapes, stream=None):
+        L = lib()
+        self.params = dict(params)
+        self.shapes = [(int(n), float(tf), int(m)) for (n, tf, m) in shapes]
+        arr = (Shape * len(self.shapes))(*[Shape(n, tf, m) for (n, tf, m) in self.shapes])
+        h = ctypes.c_void_p()
+        _check(L.traj_setup(ctypes.byref(make_params(params)), arr, len(self.shapes), _stream(stream),
+                            ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().traj_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,
+              from_state: bool = False, stream=None):
+        b = batch.c_struct()
+        s = state.c_struct()
+        flags = TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD
+        _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
+                                      flags, _stream(stream)))
+
+    def score(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, kind=0, w1=1.0, w2=1.0,
+              y_rl=None, stream=None):
+        b = batch.c_struct()
+        s = state.c_struct()
+        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl))
+        _check(lib().traj_score(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), _ptr(cost),
+                                _ptr(best), _stream(stream)))
+
+    def operators(self, shape: int):
+        """FP64 KKT inverses [5, 17, 17] and the FP32 table of one shape (host arrays)."""
+        L = lib()
+        n32 = L.traj_debug_table_size(self.handle, shape)
+        if n32 < 0:
+            _check(n32)
+        f64 = np.zeros(5 * 17 * 17, np.float64)
+        f32 = np.zeros(n32, np.float32)
+        _check(L.traj_debug_operators(self.handle, shape, f64.ctypes.data_as(ctypes.c_void_p),
+                                      f32.ctypes.data_as(ctypes.c_void_p), _stream(None)))
+        return f64.reshape(5, 17, 17), f32
+
+
+def debug_reduce(values_dev, out_dev, r, stream=None):
+    _check(lib().traj_debug_reduce(_ptr(values_dev), _ptr(out_dev), int(r), _stream(stream)))

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports what include/traj.h declares (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_10392_amd import scenes as S
+from paper_2109_10392_amd import traj as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "traj.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(traj_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for core in ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = T.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(T.EXPORTS) == set(declared_functions())
+
+
+def _params(**over):
+    return T.make_params(dict(S.DEFAULT_PARAMS, **over))
+
+
+@pytest.mark.parametrize("bad", [dict(n_coef=10), dict(rho=0.0), dict(a=-1.0), dict(v_min=0.0),
+                                 dict(v_min=40.0), dict(a_max=float("nan"))])
+def test_setup_rejects_bad_parameters_before_any_device_work(bad):
+    L = T.lib()
+    shp = (T.Shape * 1)(T.Shape(100, 10.0, 10))
+    h = ctypes.c_void_p()
+    rc = L.traj_setup(ctypes.byref(_params(**bad)), shp, 1, None, ctypes.byref(h))
+    assert rc == -1 and h.value is None
+    assert L.traj_last_error()
+
+
+@pytest.mark.parametrize("shape", [(5, 10.0, 10), (193, 10.0, 10), (100, 0.0, 10), (100, 10.0, 65), (100, 10.0, -1)])
+def test_setup_rejects_bad_shapes(shape):
+    L = T.lib()
+    shp = (T.Shape * 1)(T.Shape(*shape))
+    h = ctypes.c_void_p()
+    assert L.traj_setup(ctypes.byref(_params()), shp, 1, None, ctypes.byref(h)) == -1
+
+
+def test_null_handle_and_null_arguments_are_errors():
+    L = T.lib()
+    b = T.BatchC()
+    s = T.StateC()
+    assert L.traj_solve_batch(None, ctypes.byref(b), ctypes.byref(s), 10, 0.0, 0, None) == -1
+    assert L.traj_score(None, ctypes.byref(b), ctypes.byref(s), None, None, None, None) == -1
+    assert L.traj_destroy(None) == 0
+    assert L.traj_debug_reduce(None, None, 32, None) == -1
+    assert L.traj_setup(None, None, 0, None, None) == -1
