@@ -26,6 +26,26 @@ sys.path.insert(0, ROOT)
 N_COEF = 11
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 
+# HBM bytes per launch of the AM kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by the same counters over a plain 256 MiB copy (fetch x2.00, write
+# x1.00); see profiles/. Valid only for the kernel source they were taken on:
+# when the hash of the solver sources differs, traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "73d6ac9049164652742a34fd147004e885341ea11d831f58d4a72c960effe472",
+    "bytes_per_launch": int((351.17 * 2.0 + 568.0) * 1024),
+    "profile": "profiles/k_am_wave_dense1024.md",
+}
+SOLVER_SOURCES = ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h")
+
+
+def solver_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SOLVER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def algorithmic_flops_per_goal_iter(n, m, N=N_COEF):
     """Algorithmic FP32 work of one AM iteration of one goal (FMA = 2).
@@ -129,7 +149,9 @@ def main():
                                "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
                    "goals": B, "obstacles": m, "n_time": n, "iters": args.iters, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
+                                 if MEASURED_TRAFFIC["sources_sha256"] == solver_sources_hash() else None),
                      "kernel": "k_am (fused AM solve)", "kernel_ms": solve_avg_s * 1e3,
                      "algorithmic_flop_per_launch": flops},
         "best_goal": int(best.item()),

@@ -75,6 +75,52 @@ __device__ __forceinline__ float permlane_lo_to_hi(float v) {
   return __builtin_bit_cast(float, r0);
 }
 
+// Wave-wide minimum / maximum, returned in every lane.
+__device__ __forceinline__ float wave_min(float v) {
+  v = fminf(v, dpp<DPP_QUAD_1032>(v));
+  v = fminf(v, dpp<DPP_QUAD_2301>(v));
+  v = fminf(v, dpp<DPP_ROW_HALF_MIRROR>(v));
+  v = fminf(v, dpp<DPP_ROW_MIRROR>(v));
+  const auto a = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  v = fminf(__builtin_bit_cast(float, a0), __builtin_bit_cast(float, a1));
+  const auto b = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return fminf(__builtin_bit_cast(float, b0), __builtin_bit_cast(float, b1));
+}
+
+__device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
+
+// sin and cos: Taylor series about 0 truncated after x^15 / x^16 for |x| <= pi/2
+// (truncation error below 1e-11, i.e. FP32 rounding dominates); larger angles
+// take the library routine.
+__device__ __forceinline__ void sincos_heading(float x, float* sn, float* cs) {
+  if (fabsf(x) <= 1.5707964f) {
+    const float x2 = x * x;
+    float ps = -7.6471637e-13f;                 // -1/15!
+    ps = fmaf(ps, x2, 1.6059044e-10f);          //  1/13!
+    ps = fmaf(ps, x2, -2.5052108e-08f);         // -1/11!
+    ps = fmaf(ps, x2, 2.7557319e-06f);          //  1/9!
+    ps = fmaf(ps, x2, -1.9841270e-04f);         // -1/7!
+    ps = fmaf(ps, x2, 8.3333333e-03f);          //  1/5!
+    ps = fmaf(ps, x2, -1.6666667e-01f);         // -1/3!
+    *sn = fmaf(ps * x2, x, x);
+    float pc = 4.7794773e-14f;                  //  1/16!
+    pc = fmaf(pc, x2, -1.1470746e-11f);         // -1/14!
+    pc = fmaf(pc, x2, 2.0876757e-09f);          //  1/12!
+    pc = fmaf(pc, x2, -2.7557319e-07f);         // -1/10!
+    pc = fmaf(pc, x2, 2.4801587e-05f);          //  1/8!
+    pc = fmaf(pc, x2, -1.3888889e-03f);         // -1/6!
+    pc = fmaf(pc, x2, 4.1666667e-02f);          //  1/4!
+    pc = fmaf(pc, x2, -0.5f);                   // -1/2!
+    *cs = fmaf(pc, x2, 1.0f);
+  } else {
+    sincosf(x, sn, cs);
+  }
+}
+
 // Wave-wide sums of 32 per-lane values: on return lane l holds the sum of value l >> 1.
 __device__ __forceinline__ float reduce32(const float (&v)[32]) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -177,6 +223,7 @@ __device__ __forceinline__ void heading_input(const Lane<S>& L, const float (&cx
 // squared residual components, and e_psi = theta - psi per slot for eq. 24.
 template <int S>
 __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float2* __restrict__ xi,
+                                            const float4* __restrict__ box,
                                             const float (&cx)[NC], const float (&cy)[NC], const float (&cp)[NC],
                                             const float (&xd)[S], const float (&yd)[S], const float (&th)[S],
                                             float (&ep)[S], float (&part)[32]) {
@@ -191,27 +238,46 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     // velocity, eq. 21
     const float v = fminf(fmaxf(sqrtf(fmaf(xd[s], xd[s], yd[s] * yd[s])), G.vmin), G.vmax);
     float sn, cs;
-    sincosf(psi, &sn, &cs);
+    sincos_heading(psi, &sn, &cs);
     const float ex = fmaf(v, cs, -xd[s]), ey = fmaf(v, sn, -yd[s]);  // z - x'
     // acceleration polar variables, eq. 16: d_a = min(a_max, h), s_a = (x'', y'') (d_a / h - 1)
     const float h2 = fmaf(xdd, xdd, ydd * ydd);
     const float fa = h2 > G.amax2 ? G.amax * rsqrtf(h2) - 1.f : 0.f;
     const float sax = xdd * fa, say = ydd * fa;
     // obstacle polar variables, eqs. 15 and 22, in units scaled by (1/a, 1/b):
-    // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse
+    // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse.
+    // Only obstacles whose box over this slot's samples (inflated by the scaled
+    // half-axes plus 0.1%) meets the slot's trajectory box are visited; for every
+    // other pair (x/a - xi_x)^2 + (y/b - xi_y)^2 > 1 holds in FP32 as well, so the
+    // result is exactly that of visiting all obstacles.
     const float X = x * G.inv_a, Y = y * G.inv_b;
+    const float inf = __builtin_inff();
+    const float xlo = wave_min(L.val[s] ? X : inf), xhi = wave_max(L.val[s] ? X : -inf);
+    const float ylo = wave_min(L.val[s] ? Y : inf), yhi = wave_max(L.val[s] ? Y : -inf);
+    bool hit = false;
+    if (lane < G.m) {
+      const float4 bx = box[s * MAX_OBS + lane];
+      hit = (xhi > bx.x) && (xlo < bx.y) && (yhi > bx.z) && (ylo < bx.w);
+    }
+    unsigned long long cand = __ballot(hit);
     const int t = L.val[s] ? lane + WAVE * s : 0;
     const float2* q = xi + t;
     float Sx = 0.f, Sy = 0.f, ro = 0.f;
-    int j = 0;
-    for (; j + 4 <= G.m; j += 4) {
+    while (cand) {
+      // up to four candidates per round, their LDS reads issued together
+      int jj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jj[u] = cand ? __builtin_ctzll(cand) : -1;
+        cand &= cand - 1;
+      }
       float tx[4], ty[4], qq[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float2 o = q[(j + u) * G.n];
+        const float2 o = q[(jj[u] < 0 ? 0 : jj[u]) * G.n];
         tx[u] = X - o.x;
         ty[u] = Y - o.y;
-        qq[u] = fmaf(tx[u], tx[u], ty[u] * ty[u]);
+        qq[u] = jj[u] < 0 ? 2.f : fmaf(tx[u], tx[u], ty[u] * ty[u]);
       }
       if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
@@ -227,22 +293,6 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
               ro += G.a2;
             }
           }
-        }
-      }
-    }
-    for (; j < G.m; ++j) {
-      const float2 o = q[j * G.n];
-      const float tx = X - o.x, ty = Y - o.y;
-      const float qq = fmaf(tx, tx, ty * ty);
-      if (qq < 1.f) {
-        if (qq > 0.f) {
-          const float f = rsqrtf(qq) - 1.f;
-          Sx = fmaf(tx, f, Sx);
-          Sy = fmaf(ty, f, Sy);
-          ro = fmaf(fmaf(G.a2 * tx, tx, G.b2 * ty * ty), f * f, ro);
-        } else {
-          Sx += 1.f;
-          ro += G.a2;
         }
       }
     }
@@ -264,7 +314,8 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
 
 template <int S>
 __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float* __restrict__ T,
-                           const float2* __restrict__ xi, int scene, int g) {
+                           const float2* __restrict__ xi, const float4* __restrict__ box,
+                           const double* __restrict__ apply64, int scene, int g) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int NG = A.n_goals;
   Goal G;
@@ -301,18 +352,16 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   // Every lane computes the rows of its index k for all three applies.
   const int k_home = min((lane & 31) >> 1, NC - 1);
   const bool upper = lane >= 32;
-  // x/y step operators in FP64, heading step operator in FP32
+  // x/y step operators in FP64 (rows read from LDS when applied), heading step
+  // operator in FP32 registers
   const double* T64 = A.tables64 + sd.table64_off;
-  double rMGx[NC], rMx[NC], rMGy[NC], rMy[NC];
+  const double* rowMGx = apply64 + 0 * NC * NC + k_home * NC;
+  const double* rowMx = apply64 + 1 * NC * NC + k_home * NC;
+  const double* rowMGy = apply64 + 2 * NC * NC + k_home * NC;
+  const double* rowMy = apply64 + 3 * NC * NC + k_home * NC;
   float rMp[NC];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    rMGx[j] = T64[T64_MGX + k_home * NC + j];
-    rMx[j] = T64[T64_MX + k_home * NC + j];
-    rMGy[j] = T64[T64_MGY + k_home * NC + j];
-    rMy[j] = T64[T64_MY + k_home * NC + j];
-    rMp[j] = T[tab_square(n, SQ_MP) + k_home * NC + j];
-  }
+  for (int j = 0; j < NC; ++j) rMp[j] = T[tab_square(n, SQ_MP) + k_home * NC + j];
   // boundary values (eq. 8b) and the particular parts M_b b of each step
   const float* e = A.ego + 8 * scene;
   const float* gl = A.goal + 2 * g;
@@ -380,7 +429,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
 #pragma unroll
       for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
     }
-    projections<S>(G, L, xi, cx, cy, cp, xd, yd, th, ep, part);
+    projections<S>(G, L, xi, box, cx, cy, cp, xd, yd, th, ep, part);
     uxy = reduce32(part);
 #pragma unroll
     for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
@@ -401,8 +450,8 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       double nx = c0x, ny = c0y;
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        nx = fma(rMGx[j], (double)cx[j], fma(rMx[j], (double)rx[j], nx));
-        ny = fma(rMGy[j], (double)cy[j], fma(rMy[j], (double)ry[j], ny));
+        nx = fma(rowMGx[j], (double)cx[j], fma(rowMx[j], (double)rx[j], nx));
+        ny = fma(rowMGy[j], (double)cy[j], fma(rowMy[j], (double)ry[j], ny));
       }
       const float fx = (float)nx, fy = (float)ny;
 #pragma unroll
@@ -427,7 +476,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
     }
     // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
-    projections<S>(G, L, xi, cx, cy, cp, xd, yd, th, ep, part);
+    projections<S>(G, L, xi, box, cx, cy, cp, xd, yd, th, ep, part);
     uxy = reduce32(part);
     // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
     lxy = fmaf(rho, uxy, lxy);
@@ -527,6 +576,8 @@ __device__ void locate(const int32_t* goal_off, int n_scenes, int* sh, int* scan
 template <int S>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   extern __shared__ float2 xi[];  // [m][n] obstacle predictions, scaled by (1/a, 1/b)
+  __shared__ float4 box[S * MAX_OBS];        // per slot and obstacle: x range, y range (scaled, inflated)
+  __shared__ double apply64[4 * NC * NC];    // MGx, Mx, MGy, My of the scene's shape
   __shared__ int sh[2];
   __shared__ int scan[GOALS_PER_WG];
   locate(A.goal_off, A.n_scenes, sh, scan);
@@ -557,9 +608,28 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
     const float t = (float)i * dt;
     xi[e] = make_float2(fmaf(o[2], t, o[0]) * inv_a, fmaf(o[3], t, o[1]) * inv_b);
   }
+  // Per-slot boxes: the staged prediction is monotone in the sample index, so its
+  // extremes over a slot are at the slot's first and last sample (same expression).
+  for (int e = tid; e < S * m; e += SOLVE_THREADS) {
+    const int s = e / m, j = e - s * m;
+    const int i0 = min(WAVE * s, n - 1), i1 = min(WAVE * s + WAVE - 1, n - 1);
+    const float* o = A.obs + 4 * (o0 + j);
+    const float t0 = (float)i0 * dt, t1 = (float)i1 * dt;
+    const float xa = fmaf(o[2], t0, o[0]) * inv_a, xb = fmaf(o[2], t1, o[0]) * inv_a;
+    const float ya = fmaf(o[3], t0, o[1]) * inv_b, yb = fmaf(o[3], t1, o[1]) * inv_b;
+    constexpr float R = 1.001f;
+    box[s * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
+  }
+  const double* T64 = A.tables64 + sd.table64_off;
+  for (int e = tid; e < NC * NC; e += SOLVE_THREADS) {
+    apply64[0 * NC * NC + e] = T64[T64_MGX + e];
+    apply64[1 * NC * NC + e] = T64[T64_MX + e];
+    apply64[2 * NC * NC + e] = T64[T64_MGY + e];
+    apply64[3 * NC * NC + e] = T64[T64_MY + e];
+  }
   __syncthreads();
   if (g >= g1) return;
-  solve_goal<S>(A, sd, A.tables + sd.table_off, xi, scene, g);
+  solve_goal<S>(A, sd, A.tables + sd.table_off, xi, box, apply64, scene, g);
 }
 
 // Lane-layout check of the two reductions: in[R][64] -> out[64].
@@ -596,7 +666,7 @@ hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t st
   const int blocks = (a.n_goals + GOALS_PER_WG - 1) / GOALS_PER_WG + a.n_scenes;
   const size_t smem = sizeof(float2) * (size_t)max_n * (size_t)(max_m > 0 ? max_m : 1);
   const int S = (max_n + WAVE - 1) / WAVE;
-  if (smem > 160 * 1024) return hipErrorInvalidValue;
+  if (smem > 148 * 1024) return hipErrorInvalidValue;  // + static LDS (boxes, FP64 rows) <= 160 KiB
   const hipError_t e = (S <= 1) ? set_smem<1>(smem) : (S == 2 ? set_smem<2>(smem) : set_smem<3>(smem));
   if (e != hipSuccess) return e;
   if (S <= 1)
