@@ -82,6 +82,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-goals", type=int, default=160)
+    ap.add_argument("--kernel", choices=["auto", "wave", "mfma"], default="auto",
+                    help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--group", type=int, default=None, help="goals per matrix-core workgroup")
+    ap.add_argument("--workload", choices=["dense", "uneven"], default="dense")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -95,20 +100,32 @@ def main():
     from paper_2109_10392_amd import traj as T
 
     torch.cuda.set_device(0)
-    batch = S.workload_dense(args.seed)
+    batch = S.workload_dense(args.seed) if args.workload == "dense" else S.workload_uneven(args.seed)
     sc = batch.scenes[0]
     n, m, B = sc.n_time, sc.obs.shape[0], batch.n_goals
     solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
+    kernel = args.kernel
+    if kernel == "auto":
+        from paper_2109_10392_amd import autotune
+        tile = autotune.lookup(args.workload, args.precision)
+        kernel, group = (tile if tile is not None else ("wave", 16))
+    else:
+        group = 16
+    if args.group is not None:
+        group = args.group
+    if args.precision == "bf16x3":
+        kernel = "mfma"
+    solver.set_tile(kernel, group)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(B)
-    v_ref = torch.tensor([float(sc.ego[2])], device="cuda")
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
     cost = torch.zeros(B, device="cuda")
-    best = torch.zeros(1, device="cuda", dtype=torch.int32)
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
 
     def step(ev=None):
         if ev is not None:
             ev[0].record()
-        solver.solve(db, st, args.iters)
+        solver.solve(db, st, args.iters, precision=args.precision)
         if ev is not None:
             ev[1].record()
         solver.score(db, st, v_ref, cost, best)
@@ -130,7 +147,8 @@ def main():
     ms_per_step = total_ms / args.steps
     value = B * args.iters * args.steps / (total_ms / 1e3)
     solve_avg_s = sum(solve_ms) / len(solve_ms) / 1e3
-    flops = algorithmic_flops_per_goal_iter(n, m) * B * args.iters
+    flops = sum(algorithmic_flops_per_goal_iter(s.n_time, s.obs.shape[0]) * s.goals.shape[0]
+                for s in batch.scenes) * args.iters
     achieved = flops / solve_avg_s / 1e12
     out = {
         "metric": "goal-trajectories*iters/s",
@@ -143,11 +161,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
         "data": "synthetic",
-        "config": {"workload": "dense highway scene: 1 scene x 1024 goals, 50 obstacles, 6 lanes, "
-                               "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
-                   "goals": B, "obstacles": m, "n_time": n, "iters": args.iters, "seed": args.seed},
+        "config": ({"workload": "dense highway scene: 1 scene x 1024 goals, 50 obstacles, 6 lanes, "
+                                "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
+                    "goals": B, "obstacles": m, "n_time": n}
+                   if args.workload == "dense" else
+                   {"workload": "uneven batch: 512 scenes, goals log-uniform 16-1024, obstacles U{4..64}, "
+                                "T in {50,100,150}, 100 AM iterations (cold start) + scoring",
+                    "goals": B, "scenes": batch.n_scenes})
+        | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
@@ -156,7 +179,7 @@ def main():
                      "algorithmic_flop_per_launch": flops},
         "best_goal": int(best.item()),
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "dense":
         out["cpu_baseline"] = cpu_baseline(sc, args.iters, args.cpu_goals)
     solver.close()
     print(json.dumps(out), flush=True)

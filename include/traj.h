@@ -39,6 +39,12 @@ extern "C" {
 /* traj_solve_batch flags */
 #define TRAJ_INIT_COLD 0x0u       /* cold start (boundary-only minimum-acceleration QP)      */
 #define TRAJ_INIT_FROM_STATE 0x1u /* start from (c, lam) in the state (resume, warm start)   */
+#define TRAJ_PREC_FP32 0x0u       /* FP32 arithmetic, x/y step operators in FP64 (default)   */
+#define TRAJ_PREC_BF16X3 0x10u    /* matrix-core kernel, every contraction and apply in split
+                                     BF16 (hi + lo, three products) with FP32 accumulation   */
+#define TRAJ_KERNEL_AUTO 0x0u     /* kernel from the handle's tile setting (traj_set_tile)   */
+#define TRAJ_KERNEL_WAVE 0x100u   /* one wavefront per goal, lanes over time                 */
+#define TRAJ_KERNEL_MFMA 0x200u   /* matrix-core kernel: goal groups x 16-sample time tiles  */
 
 #define TRAJ_N_COEF 11 /* Bernstein degree 10: coefficients per axis */
 
@@ -113,9 +119,12 @@ int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes
  * convex surrogate (eq. 13 via eq. 20), velocity (eq. 21), obstacle polar
  * variables (eq. 22 and the clipped 1-D minimiser of eq. 15), acceleration polar
  * variables (eq. 16), multipliers (eqs. 23-24).
- *   flags: TRAJ_INIT_COLD or TRAJ_INIT_FROM_STATE.
- *   tol: <= 0 runs exactly `iters` iterations; > 0 stops a goal at the first
- *        multiple of 5 iterations where max(r_obs, r_acc, r_nh) <= tol.
+ *   flags: TRAJ_INIT_COLD or TRAJ_INIT_FROM_STATE, | TRAJ_PREC_FP32 or
+ *          TRAJ_PREC_BF16X3, | TRAJ_KERNEL_AUTO, TRAJ_KERNEL_WAVE or
+ *          TRAJ_KERNEL_MFMA (BF16X3 always runs on the matrix-core kernel).
+ *   tol: <= 0 runs exactly `iters` iterations; > 0 stops at the first multiple
+ *        of 5 iterations where max(r_obs, r_acc, r_nh) <= tol: per goal in the
+ *        wave kernel, per goal group (all of its goals) in the matrix-core kernel.
  *   iters: 0 <= iters <= 100000. n_goals == 0 is a no-op.
  * Shape mismatches found on the device (unknown shape id, wrong obstacle count)
  * set that scene's residuals to NaN; nothing aborts.
@@ -135,6 +144,23 @@ int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, i
  */
 int traj_score(void *handle, const traj_batch *batch, const traj_state *state, const traj_metacost *mc,
                float *cost, int32_t *best, void *stream);
+
+/* Kernel tile of a handle. kernel: TRAJ_KERNEL_WAVE or TRAJ_KERNEL_MFMA; group:
+ * goals per matrix-core workgroup, 1..16 (the MFMA has 16 goal columns; fewer
+ * goals per group spread a small batch over more compute units). */
+typedef struct {
+  int32_t kernel;
+  int32_t group;
+} traj_tile;
+
+/*
+ * traj_set_tile / traj_get_tile -- the tile used when traj_solve_batch is called
+ * with TRAJ_KERNEL_AUTO (the default). Chosen by the autotuner for a workload;
+ * the initial setting is {TRAJ_KERNEL_WAVE, 16}. Host-only, no device work.
+ * Errors: TRAJ_E_INVAL (unknown kernel, group outside 1..16).
+ */
+int traj_set_tile(void *handle, const traj_tile *tile);
+int traj_get_tile(void *handle, traj_tile *tile);
 
 /* traj_destroy -- free the handle's device memory. NULL is a no-op. */
 int traj_destroy(void *handle);

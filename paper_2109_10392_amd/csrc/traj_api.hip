@@ -43,6 +43,7 @@ struct Handle {
   double* d_tables64 = nullptr;
   int max_n = 0, max_m = 0;
   size_t table_floats = 0;
+  traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16};
 };
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
@@ -152,7 +153,12 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   if (state == nullptr) return fail(TRAJ_E_INVAL, "state is NULL");
   if (iters < 0 || iters > 100000) return fail(TRAJ_E_INVAL, "iters must be in [0, 100000]");
   if (!isfinite(tol)) return fail(TRAJ_E_INVAL, "tol must be finite");
-  if ((flags & ~TRAJ_INIT_FROM_STATE) != 0) return fail(TRAJ_E_INVAL, "unknown flags 0x%x", flags);
+  const uint32_t known = TRAJ_INIT_FROM_STATE | TRAJ_PREC_BF16X3 | TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA;
+  if ((flags & ~known) != 0) return fail(TRAJ_E_INVAL, "unknown flags 0x%x", flags);
+  if ((flags & TRAJ_KERNEL_WAVE) && (flags & TRAJ_KERNEL_MFMA))
+    return fail(TRAJ_E_INVAL, "TRAJ_KERNEL_WAVE and TRAJ_KERNEL_MFMA are exclusive");
+  if ((flags & TRAJ_PREC_BF16X3) && (flags & TRAJ_KERNEL_WAVE))
+    return fail(TRAJ_E_INVAL, "TRAJ_PREC_BF16X3 runs on the matrix-core kernel only");
   if (batch->n_goals == 0) return TRAJ_OK;
   if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
   traj::SolveArgs a;
@@ -176,7 +182,15 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   a.flags = (int)flags;
   a.tol = tol;
   a.k = consts(h->p);
-  hipError_t e = traj::launch_solve(a, h->max_n, h->max_m, (hipStream_t)stream);
+  bool mfma = (flags & TRAJ_PREC_BF16X3) || (flags & TRAJ_KERNEL_MFMA) ||
+              (!(flags & TRAJ_KERNEL_WAVE) && h->tile.kernel == (int32_t)TRAJ_KERNEL_MFMA);
+  hipError_t e;
+  if (mfma) {
+    const int mode = (flags & TRAJ_PREC_BF16X3) ? traj::TRAJ_MODE_BF16X3 : traj::TRAJ_MODE_FP32;
+    e = traj::launch_solve_mfma(a, mode, h->tile.group, h->max_n, h->max_m, (hipStream_t)stream);
+  } else {
+    e = traj::launch_solve(a, h->max_n, h->max_m, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "traj_solve_batch launch");
   return TRAJ_OK;
 }
@@ -215,6 +229,25 @@ int traj_score(void* handle, const traj_batch* batch, const traj_state* state, c
   a.best = best;
   hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "traj_score launch");
+  return TRAJ_OK;
+}
+
+int traj_set_tile(void* handle, const traj_tile* tile) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr || tile == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
+  if (tile->kernel != (int32_t)TRAJ_KERNEL_WAVE && tile->kernel != (int32_t)TRAJ_KERNEL_MFMA)
+    return fail(TRAJ_E_INVAL, "unknown kernel 0x%x", (unsigned)tile->kernel);
+  if (tile->group < 1 || tile->group > 16) return fail(TRAJ_E_INVAL, "group must be in [1, 16]");
+  h->tile = *tile;
+  return TRAJ_OK;
+}
+
+int traj_get_tile(void* handle, traj_tile* tile) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr || tile == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
+  *tile = h->tile;
   return TRAJ_OK;
 }
 

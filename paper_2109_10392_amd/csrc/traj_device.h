@@ -1,0 +1,182 @@
+// Device helpers shared by the solver kernels: cross-lane primitives of gfx950
+// (DPP row/quad permutations, permlane16/32 swaps), wave reductions and the
+// workgroup -> scene lookup.
+#pragma once
+#include "traj_internal.h"
+
+namespace traj {
+namespace dev {
+
+constexpr int DPP_QUAD_1032 = 0xB1;  // quad_perm [1,0,3,2]: partner lane ^ 1
+constexpr int DPP_QUAD_2301 = 0x4E;  // quad_perm [2,3,0,1]: partner lane ^ 2
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane p <-> 15 - p within a row of 16
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane p <-> 7 - p within a half-row of 8
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// lanes 0-31 of the result: a summed over lane pairs (l, l+32); lanes 32-63: b summed likewise
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  // copy the two results out as values first: a bit_cast of the vector element
+  // lvalue r[1] is lowered as element 0 by this compiler
+  const unsigned r0 = r[0], r1 = r[1];
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
+// within each 32-lane half: lanes 0-15 a summed over (l, l+16), lanes 16-31 b summed likewise
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  const unsigned r0 = r[0], r1 = r[1];
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
+// lanes 32-63 receive lanes 0-31 of v (lanes 0-31 keep v)
+__device__ __forceinline__ float permlane_lo_to_hi(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned r0 = r[0];
+  return __builtin_bit_cast(float, r0);
+}
+
+// Wave-wide minimum / maximum, returned in every lane.
+__device__ __forceinline__ float wave_min(float v) {
+  v = fminf(v, dpp<DPP_QUAD_1032>(v));
+  v = fminf(v, dpp<DPP_QUAD_2301>(v));
+  v = fminf(v, dpp<DPP_ROW_HALF_MIRROR>(v));
+  v = fminf(v, dpp<DPP_ROW_MIRROR>(v));
+  const auto a = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  v = fminf(__builtin_bit_cast(float, a0), __builtin_bit_cast(float, a1));
+  const auto b = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return fminf(__builtin_bit_cast(float, b0), __builtin_bit_cast(float, b1));
+}
+
+__device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
+
+// sin and cos: Taylor series about 0 truncated after x^15 / x^16 for |x| <= pi/2
+// (truncation error below 1e-11, i.e. FP32 rounding dominates); larger angles
+// take the library routine.
+__device__ __forceinline__ void sincos_heading(float x, float* sn, float* cs) {
+  if (fabsf(x) <= 1.5707964f) {
+    const float x2 = x * x;
+    float ps = -7.6471637e-13f;                 // -1/15!
+    ps = fmaf(ps, x2, 1.6059044e-10f);          //  1/13!
+    ps = fmaf(ps, x2, -2.5052108e-08f);         // -1/11!
+    ps = fmaf(ps, x2, 2.7557319e-06f);          //  1/9!
+    ps = fmaf(ps, x2, -1.9841270e-04f);         // -1/7!
+    ps = fmaf(ps, x2, 8.3333333e-03f);          //  1/5!
+    ps = fmaf(ps, x2, -1.6666667e-01f);         // -1/3!
+    *sn = fmaf(ps * x2, x, x);
+    float pc = 4.7794773e-14f;                  //  1/16!
+    pc = fmaf(pc, x2, -1.1470746e-11f);         // -1/14!
+    pc = fmaf(pc, x2, 2.0876757e-09f);          //  1/12!
+    pc = fmaf(pc, x2, -2.7557319e-07f);         // -1/10!
+    pc = fmaf(pc, x2, 2.4801587e-05f);          //  1/8!
+    pc = fmaf(pc, x2, -1.3888889e-03f);         // -1/6!
+    pc = fmaf(pc, x2, 4.1666667e-02f);          //  1/4!
+    pc = fmaf(pc, x2, -0.5f);                   // -1/2!
+    *cs = fmaf(pc, x2, 1.0f);
+  } else {
+    sincosf(x, sn, cs);
+  }
+}
+
+// Wave-wide sums of 32 per-lane values: on return lane l holds the sum of value l >> 1.
+__device__ __forceinline__ float reduce32(const float (&v)[32]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  float s[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s[i] = swap32_add(v[i], v[i + 16]);
+  float t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = swap16_add(s[i], s[i + 8]);
+  const bool lo8 = (lane & 8) == 0;
+  float u[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = (lo8 ? t[i] : t[i + 4]) + dpp<DPP_ROW_MIRROR>(lo8 ? t[i + 4] : t[i]);
+  const bool lo4 = (lane & 4) == 0;
+  float w[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) w[i] = (lo4 ? u[i] : u[i + 2]) + dpp<DPP_ROW_HALF_MIRROR>(lo4 ? u[i + 2] : u[i]);
+  const bool lo2 = (lane & 2) == 0;
+  float z = (lo2 ? w[0] : w[1]) + dpp<DPP_QUAD_2301>(lo2 ? w[1] : w[0]);
+  return z + dpp<DPP_QUAD_1032>(z);
+}
+
+// Wave-wide sums of 16 per-lane values: on return lane l holds the sum of value l >> 2.
+__device__ __forceinline__ float reduce16(const float (&v)[16]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  float s[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s[i] = swap32_add(v[i], v[i + 8]);
+  float t[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[i] = swap16_add(s[i], s[i + 4]);
+  const bool lo8 = (lane & 8) == 0;
+  float u[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) u[i] = (lo8 ? t[i] : t[i + 2]) + dpp<DPP_ROW_MIRROR>(lo8 ? t[i + 2] : t[i]);
+  const bool lo4 = (lane & 4) == 0;
+  float z = (lo4 ? u[0] : u[1]) + dpp<DPP_ROW_HALF_MIRROR>(lo4 ? u[1] : u[0]);
+  z += dpp<DPP_QUAD_2301>(z);
+  return z + dpp<DPP_QUAD_1032>(z);
+}
+
+
+// Workgroup -> (scene, first goal): scene s owns ceil(goals_s / per_item)
+// consecutive workgroups. Returns scene -1 past the last one. scan needs one
+// int per wave of the workgroup.
+__device__ void locate(const int32_t* goal_off, int n_scenes, int per_item, int* sh, int* scan) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1), wv = tid >> 6;
+  if (tid == 0) {
+    sh[0] = -1;
+    sh[1] = 0;
+  }
+  int base = 0;
+  for (int c0 = 0; c0 < n_scenes; c0 += (int)blockDim.x) {
+    const int s = c0 + tid;
+    const int cnt = (s < n_scenes) ? (goal_off[s + 1] - goal_off[s] + per_item - 1) / per_item : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const int y = __shfl_up(incl, d, WAVE);
+      if (lane >= d) incl += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) scan[wv] = incl;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    const int nw = (int)blockDim.x / WAVE;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wv) pre += scan[w];
+      tot += scan[w];
+    }
+    incl += pre;
+    const int excl = incl - cnt;
+    const int b = (int)blockIdx.x - base;
+    if (cnt > 0 && b >= excl && b < incl) {
+      sh[0] = s;
+      sh[1] = goal_off[s] + per_item * (b - excl);
+    }
+    base += tot;
+    if (base > (int)blockIdx.x) break;  // uniform: every thread sees the same base
+  }
+  __syncthreads();
+}
+
+
+}  // namespace dev
+}  // namespace traj

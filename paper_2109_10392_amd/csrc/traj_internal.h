@@ -17,6 +17,10 @@ constexpr int MAX_OBS = 64;
 constexpr int WAVE = 64;
 constexpr int GOALS_PER_WG = 4;  // one goal per wave, four waves per workgroup
 
+// precision modes of the matrix-core kernel
+constexpr int TRAJ_MODE_FP32 = 0;
+constexpr int TRAJ_MODE_BF16X3 = 1;
+
 // Per-shape FP32 table, offsets in floats from the shape's table_off.
 //   basis:  P[NC][n], Pd[NC][n], Pdd[NC][n]        (coefficient-major, time fastest)
 //   square: MGx, Mx, MGy, My, Mp                   (each NC x NC row-major)
@@ -108,6 +112,8 @@ struct ScoreArgs {
 hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverConst& k, float* d_tables,
                         double* d_tables64, int max_n, hipStream_t stream);
 hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t stream);
+hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
+size_t mfma_smem_bytes(int max_n, int max_m);
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
 
 }  // namespace traj

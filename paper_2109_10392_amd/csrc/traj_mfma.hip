@@ -1,0 +1,650 @@
+// Batched alternating minimisation (Algorithm 1, Sec. III-D) on the matrix cores.
+//
+// Mapping: one workgroup per goal group (up to 16 goals of one scene: the MFMA
+// columns), one wavefront per 16-sample time tile (the MFMA rows). Every dense
+// contraction of the method runs on MFMA:
+//   basis evaluation    X[t][goal] = sum_k P[t][k] c[k][goal]          (eq. 6)
+//   time contractions   U[k][goal] = sum_t P[t][k] S[t][goal]          (F^T g of eq. 18, P^T theta of eq. 20)
+//   inverse x RHS       c_new[k][goal] = sum_i M[k][i] r[i][goal]       (eqs. 18, 20)
+// with the goal index as the MFMA column. The per-sample closed forms (eqs. 21,
+// 22, 15, 16) run on the vector ALU over each lane's 4 samples. A contraction's
+// partial sums over one tile are added across the workgroup's waves through LDS
+// in a fixed order, so every wave holds the same totals and repeats the small
+// applies itself.
+//
+// Lane l of a wave: column (goal) j = l % 16, row group q = l / 16. It holds the
+// MFMA output rows 4q + r (r = 0..3): time samples 16 w + 4q + r of goal j after
+// an evaluation, coefficients 4q + r of goal j after a contraction or apply. The
+// K index of every product is chosen so that a lane's operands are exactly the
+// values it already holds; the constant operands are permuted to match.
+//
+// Two precisions:
+//   FP32:   v_mfma_f32_16x16x4_f32 for evaluations, contractions and the heading
+//           apply; v_mfma_f64_16x16x4_f64 for the x/y applies (their constant
+//           operators stay FP64, as in the wave kernel).
+//   BF16x3: v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo (bf16 each):
+//           hi*hi + lo*hi + hi*lo in two instructions (K = 32 holds hi and lo of
+//           16 K values), FP32 accumulation, for every contraction and apply.
+#include "traj_device.h"
+
+namespace traj {
+namespace {
+
+using namespace dev;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int TILE = 16;  // time samples per wave
+constexpr int GCOLS = 16;  // goals per MFMA
+
+__device__ __forceinline__ f4 mma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mmabf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ __bf16 bf_hi(float x) { return (__bf16)x; }
+__device__ __forceinline__ __bf16 bf_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
+
+// B operand of a split product from the lane's 4 values: K slots 8q + e hold
+// hi(v[e]) for e < 4 and lo(v[e - 4]) for e >= 4.
+__device__ __forceinline__ bf8 split_b(const f4& v) {
+  bf8 b;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    b[e] = bf_hi(v[e]);
+    b[e + 4] = bf_lo(v[e]);
+  }
+  return b;
+}
+// A operands of a split product from 4 values a[e] (K slots 8q + e and 8q + e + 4):
+// first instruction hi(a) against (hi, lo) of B, second lo(a) against hi of B.
+__device__ __forceinline__ void split_a(const float (&a)[4], bf8& first, bf8& second) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    first[e] = bf_hi(a[e]);
+    first[e + 4] = bf_hi(a[e]);
+    second[e] = bf_lo(a[e]);
+    second[e + 4] = (__bf16)0.f;
+  }
+}
+
+template <int MODE>
+struct Ops;
+
+// FP32: per matrix 4 K-steps of one float each.
+template <>
+struct Ops<TRAJ_MODE_FP32> {
+  float ev[3][4];   // evaluation: P, P', P'' [t = 16w + j][4q + kk]
+  float ct[3][4];   // contraction: P, P', P'' [16w + 4q + r][j]
+  double mgx[4], mx[4], mgy[4], my[4];  // x/y applies (rows permuted for the f64 output layout)
+  float mp[4];      // heading apply
+};
+
+// BF16x3: per matrix two split instructions.
+template <>
+struct Ops<TRAJ_MODE_BF16X3> {
+  bf8 ev[3][2];
+  bf8 ct[3][2];
+  bf8 mgx[2], mx[2], mgy[2], my[2], mp[2];
+};
+
+// evaluation of matrix `mi` at the lane's 4 samples for coefficients c (rows 4q + r)
+template <int MODE>
+__device__ __forceinline__ f4 eval(const Ops<MODE>& O, int mi, const f4& c, const bf8& cb) {
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.ev[mi][kk], c[kk], acc);
+  } else {
+    acc = mmabf(O.ev[mi][0], cb, acc);
+    acc = mmabf(O.ev[mi][1], cb, acc);
+  }
+  return acc;
+}
+
+// accumulate the contraction of matrix `mi` against per-sample values s (lane's 4 samples)
+template <int MODE>
+__device__ __forceinline__ f4 contract(const Ops<MODE>& O, int mi, const f4& s, f4 acc) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = mma32(O.ct[mi][r], s[r], acc);
+  } else {
+    const bf8 sb = split_b(s);
+    acc = mmabf(O.ct[mi][0], sb, acc);
+    acc = mmabf(O.ct[mi][1], sb, acc);
+  }
+  return acc;
+}
+
+// c0 + MG c + M r for one axis
+template <int MODE>
+__device__ __forceinline__ f4 apply_xy(const Ops<MODE>& O, int axis, const d4& c0d, const f4& c0f, const f4& c,
+                                       const f4& r) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+    const double* mg = axis == 0 ? O.mgx : O.mgy;
+    const double* m = axis == 0 ? O.mx : O.my;
+    d4 acc = c0d;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma64(mg[kk], (double)c[kk], acc);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma64(m[kk], (double)r[kk], acc);
+    f4 out;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = (float)acc[k];
+    return out;
+  } else {
+    const bf8* mg = axis == 0 ? O.mgx : O.mgy;
+    const bf8* m = axis == 0 ? O.mx : O.my;
+    const bf8 cb = split_b(c), rb = split_b(r);
+    f4 acc = c0f;
+    acc = mmabf(mg[0], cb, acc);
+    acc = mmabf(mg[1], cb, acc);
+    acc = mmabf(m[0], rb, acc);
+    acc = mmabf(m[1], rb, acc);
+    return acc;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ f4 apply_psi(const Ops<MODE>& O, const f4& c0p, const f4& r) {
+  f4 acc = c0p;
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.mp[kk], r[kk], acc);
+  } else {
+    const bf8 rb = split_b(r);
+    acc = mmabf(O.mp[0], rb, acc);
+    acc = mmabf(O.mp[1], rb, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ float4 f4to(const f4& v) { return make_float4(v[0], v[1], v[2], v[3]); }
+__device__ __forceinline__ f4 tof4(const float4& v) {
+  f4 r = {v.x, v.y, v.z, v.w};
+  return r;
+}
+
+// Sum two per-lane vectors over the workgroup's waves (fixed order: identical in
+// every wave). ex: [2 buffers][W][2][64] float4.
+__device__ __forceinline__ void exchange(float4* ex, int buf, int W, int w, int lane, f4& a, f4& b) {
+  float4* mine = ex + ((size_t)(buf * W + w) * 2) * WAVE;
+  mine[lane] = f4to(a);
+  mine[WAVE + lane] = f4to(b);
+  __syncthreads();
+  f4 sa = {0.f, 0.f, 0.f, 0.f}, sb = {0.f, 0.f, 0.f, 0.f};
+  for (int v = 0; v < W; ++v) {
+    const float4* p = ex + ((size_t)(buf * W + v) * 2) * WAVE;
+    sa += tof4(p[lane]);
+    sb += tof4(p[WAVE + lane]);
+  }
+  a = sa;
+  b = sb;
+}
+
+// sum over the 4 row groups (lanes j, j+16, j+32, j+48), result in every lane
+__device__ __forceinline__ float sum_rows(float v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  const float s = __builtin_bit_cast(float, a0) + __builtin_bit_cast(float, a1);
+  const auto b = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, s), __builtin_bit_cast(unsigned, s),
+                                                  false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return __builtin_bit_cast(float, b0) + __builtin_bit_cast(float, b1);
+}
+
+struct Consts {
+  int n, m, n_pad, W;
+  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2;
+};
+
+template <int MODE>
+__device__ void load_ops(Ops<MODE>& O, const float* __restrict__ T, const double* __restrict__ T64, int n, int w,
+                         int j, int q) {
+  // row-permutation of the f64 16x16x4 output: register r of row group q is row 4r + q
+  const int prow = 4 * (j & 3) + (j >> 2);
+#pragma unroll
+  for (int mi = 0; mi < 3; ++mi) {
+    float ev[4], ct[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int t = TILE * w + j, k = 4 * q + kk;
+      ev[kk] = (t < n && k < NC) ? T[tab_basis(n, mi) + k * n + t] : 0.f;
+      const int t2 = TILE * w + 4 * q + kk;
+      ct[kk] = (t2 < n && j < NC) ? T[tab_basis(n, mi) + j * n + t2] : 0.f;
+    }
+    if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        O.ev[mi][kk] = ev[kk];
+        O.ct[mi][kk] = ct[kk];
+      }
+    } else {
+      split_a(ev, O.ev[mi][0], O.ev[mi][1]);
+      split_a(ct, O.ct[mi][0], O.ct[mi][1]);
+    }
+  }
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * q + kk;
+      const bool ok = prow < NC && k < NC;
+      O.mgx[kk] = ok ? T64[T64_MGX + prow * NC + k] : 0.0;
+      O.mx[kk] = ok ? T64[T64_MX + prow * NC + k] : 0.0;
+      O.mgy[kk] = ok ? T64[T64_MGY + prow * NC + k] : 0.0;
+      O.my[kk] = ok ? T64[T64_MY + prow * NC + k] : 0.0;
+      O.mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
+    }
+  } else {
+    float mgx[4], mx[4], mgy[4], my[4], mp[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * q + kk;
+      const bool ok = j < NC && k < NC;
+      mgx[kk] = ok ? (float)T64[T64_MGX + j * NC + k] : 0.f;
+      mx[kk] = ok ? (float)T64[T64_MX + j * NC + k] : 0.f;
+      mgy[kk] = ok ? (float)T64[T64_MGY + j * NC + k] : 0.f;
+      my[kk] = ok ? (float)T64[T64_MY + j * NC + k] : 0.f;
+      mp[kk] = ok ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
+    }
+    split_a(mgx, O.mgx[0], O.mgx[1]);
+    split_a(mx, O.mx[0], O.mx[1]);
+    split_a(mgy, O.mgy[0], O.mgy[1]);
+    split_a(my, O.my[0], O.my[1]);
+    split_a(mp, O.mp[0], O.mp[1]);
+  }
+}
+
+// Per-sample closed forms for the lane's 4 samples and the contraction inputs.
+struct SampleOut {
+  f4 sox, soy, sax, say, ex, ey, ep;
+  float r_obs, r_acc, r_nh, r_psi;
+};
+
+__device__ __forceinline__ void samples(const Consts& K, const float2* __restrict__ xi, const float4* __restrict__ box,
+                                        int w, int lane, int q, bool gv, const f4& x, const f4& y, const f4& xd,
+                                        const f4& yd, const f4& xdd, const f4& ydd, const f4& psi, const f4& th,
+                                        SampleOut& o) {
+  bool tv[4];
+  float X[4], Y[4];
+  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+  o.r_obs = o.r_acc = o.r_nh = o.r_psi = 0.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    tv[r] = gv && (TILE * w + 4 * q + r) < K.n;
+    X[r] = x[r] * K.inv_a;
+    Y[r] = y[r] * K.inv_b;
+    if (tv[r]) {
+      lxlo = fminf(lxlo, X[r]);
+      lxhi = fmaxf(lxhi, X[r]);
+      lylo = fminf(lylo, Y[r]);
+      lyhi = fmaxf(lyhi, Y[r]);
+    }
+    // velocity (eq. 21), heading direction, z - x'
+    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
+    float sn, cs;
+    sincos_heading(psi[r], &sn, &cs);
+    const float ex = fmaf(v, cs, -xd[r]), ey = fmaf(v, sn, -yd[r]);
+    // acceleration polar variables (eq. 16)
+    const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
+    const float fa = h2 > K.amax2 ? K.amax * rsqrtf(h2) - 1.f : 0.f;
+    const float sax = xdd[r] * fa, say = ydd[r] * fa;
+    const float ep = th[r] - psi[r];
+    o.ex[r] = tv[r] ? ex : 0.f;
+    o.ey[r] = tv[r] ? ey : 0.f;
+    o.sax[r] = tv[r] ? sax : 0.f;
+    o.say[r] = tv[r] ? say : 0.f;
+    o.ep[r] = tv[r] ? ep : 0.f;
+    if (tv[r]) {
+      o.r_acc = fmaf(sax, sax, fmaf(say, say, o.r_acc));
+      o.r_nh = fmaf(ex, ex, fmaf(ey, ey, o.r_nh));
+      o.r_psi = fmaf(ep, ep, o.r_psi);
+    }
+  }
+  // obstacle polar variables (eqs. 15, 22) with exact culling against the
+  // tile's obstacle boxes (inflated by the scaled half-axes + 0.1%)
+  const float xlo = wave_min(lxlo), xhi = wave_max(lxhi), ylo = wave_min(lylo), yhi = wave_max(lyhi);
+  bool hit = false;
+  if (lane < K.m) {
+    const float4 bx = box[w * K.m + lane];
+    hit = (xhi > bx.x) && (xlo < bx.y) && (yhi > bx.z) && (ylo < bx.w);
+  }
+  unsigned long long cand = __ballot(hit);
+  float Sx[4] = {0.f, 0.f, 0.f, 0.f}, Sy[4] = {0.f, 0.f, 0.f, 0.f};
+  const float2* base = xi + TILE * w + 4 * q;
+  while (cand) {
+    const int jo = __builtin_ctzll(cand);
+    cand &= cand - 1;
+    const float4* p = reinterpret_cast<const float4*>(base + jo * K.n_pad);
+    const float4 o01 = p[0], o23 = p[1];
+    const float ox[4] = {o01.x, o01.z, o23.x, o23.z};
+    const float oy[4] = {o01.y, o01.w, o23.y, o23.w};
+    float tx[4], ty[4], qq[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tx[r] = X[r] - ox[r];
+      ty[r] = Y[r] - oy[r];
+      qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
+    }
+    if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (qq[r] < 1.f) {
+          if (qq[r] > 0.f) {
+            const float f = rsqrtf(qq[r]) - 1.f;
+            Sx[r] = fmaf(tx[r], f, Sx[r]);
+            Sy[r] = fmaf(ty[r], f, Sy[r]);
+            o.r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, o.r_obs);
+          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
+            Sx[r] += 1.f;
+            o.r_obs += K.a2;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    o.sox[r] = K.a * Sx[r];
+    o.soy[r] = K.b * Sy[r];
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh[2];
+  __shared__ int scan[16];
+  const int Wl = (int)blockDim.x / WAVE;  // waves launched
+  locate(A.goal_off, A.n_scenes, G, sh, scan);
+  const int scene = sh[0];
+  if (scene < 0) return;
+  const int g0 = sh[1];
+  const int gcount = min(min(G, (int)A.goal_off[scene + 1] - g0), A.n_goals - g0);
+  const int sid = A.shape_id[scene];
+  const int o0 = A.obs_off[scene];
+  const int m_scene = A.obs_off[scene + 1] - o0;
+  bool bad = sid < 0 || sid >= A.n_shapes;
+  ShapeDesc sd = {};
+  if (!bad) sd = A.shapes[sid];
+  bad = bad || m_scene != sd.m || sd.n < NC || (sd.n + TILE - 1) / TILE > Wl;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
+  const int j = lane & 15, q = lane >> 4;
+  if (bad) {
+    if (w == 0 && q < 1 && j < gcount) {
+      if (A.resid != nullptr)
+        for (int k = 0; k < 4; ++k) A.resid[k * A.n_goals + g0 + j] = __builtin_nanf("");
+      if (A.iters_out != nullptr) A.iters_out[g0 + j] = 0;
+    }
+    return;
+  }
+  Consts K;
+  K.n = sd.n;
+  K.m = sd.m;
+  K.W = Wl;
+  K.n_pad = TILE * Wl;
+  K.rho = A.k.rho;
+  K.a = A.k.a;
+  K.b = A.k.b;
+  K.inv_a = 1.f / K.a;
+  K.inv_b = 1.f / K.b;
+  K.a2 = K.a * K.a;
+  K.b2 = K.b * K.b;
+  K.vmin = A.k.v_min;
+  K.vmax = A.k.v_max;
+  K.amax = A.k.a_max;
+  K.amax2 = K.amax * K.amax;
+  const int n = K.n, m = K.m;
+  // LDS: xi [m][n_pad] float2 | box [W][m] float4 | exchange [2][W][2][64] float4
+  float2* xi = reinterpret_cast<float2*>(smem);
+  float4* box = reinterpret_cast<float4*>(smem + sizeof(float2) * (size_t)m * K.n_pad);
+  float4* ex = box + (size_t)Wl * m;
+  {
+    const float dt = sd.t_f / (float)(n - 1);
+    for (int e = tid; e < m * K.n_pad; e += blockDim.x) {
+      const int jo = e / K.n_pad, i = e - jo * K.n_pad;
+      const float* o = A.obs + 4 * (o0 + jo);
+      if (i < n) {
+        const float t = (float)i * dt;
+        xi[e] = make_float2(fmaf(o[2], t, o[0]) * K.inv_a, fmaf(o[3], t, o[1]) * K.inv_b);
+      } else {
+        xi[e] = make_float2(1e30f, 1e30f);
+      }
+    }
+    for (int e = tid; e < Wl * m; e += blockDim.x) {
+      const int ww = e / m, jo = e - ww * m;
+      const int i0 = min(TILE * ww, n - 1), i1 = min(TILE * ww + TILE - 1, n - 1);
+      const float* o = A.obs + 4 * (o0 + jo);
+      const float t0 = (float)i0 * dt, t1 = (float)i1 * dt;
+      const float xa = fmaf(o[2], t0, o[0]) * K.inv_a, xb = fmaf(o[2], t1, o[0]) * K.inv_a;
+      const float ya = fmaf(o[3], t0, o[1]) * K.inv_b, yb = fmaf(o[3], t1, o[1]) * K.inv_b;
+      constexpr float R = 1.001f;
+      box[e] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
+    }
+  }
+  __syncthreads();
+
+  const float* T = A.tables + sd.table_off;
+  const double* T64 = A.tables64 + sd.table64_off;
+  Ops<MODE> O;
+  load_ops<MODE>(O, T, T64, n, w, j, q);
+  const bool gv = j < gcount;
+  const int g = g0 + (gv ? j : 0);
+  const int NG = A.n_goals;
+  const float rho = K.rho;
+
+  // boundary values (eq. 8b) and the particular parts M_b b of each step (rows 4q + r)
+  const float* e = A.ego + 8 * scene;
+  const float* gl = A.goal + 2 * g;
+  const float bx[NX] = {e[0], e[2], e[4], gl[0]};
+  const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
+  const float bp[NP] = {e[6], e[7], 0.f, 0.f};
+  const float* Bt = T + tab_bnd(n);
+  d4 c0xd = {0.0, 0.0, 0.0, 0.0}, c0yd = {0.0, 0.0, 0.0, 0.0};
+  f4 c0xf = {0.f, 0.f, 0.f, 0.f}, c0yf = c0xf, c0p = c0xf;
+  f4 cx = c0xf, cy = c0xf, cp = c0xf, lx = c0xf, ly = c0xf, lp = c0xf;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k = 4 * q + r;
+    if (k < NC) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
+      for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
+      c0xd[r] = sx;
+      c0yd[r] = sy;
+      c0xf[r] = (float)sx;
+      c0yf[r] = (float)sy;
+      float sp = 0.f;
+      for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
+      c0p[r] = sp;
+    }
+  }
+  const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
+  if (cold) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        float sx = 0.f, sy = 0.f;
+        for (int i = 0; i < NX; ++i) sx = fmaf(Bt[BND_M0BX + k * NX + i], bx[i], sx);
+        for (int i = 0; i < NY; ++i) sy = fmaf(Bt[BND_M0BY + k * NY + i], by[i], sy);
+        cx[r] = sx;
+        cy[r] = sy;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        cx[r] = A.c[(0 * NC + k) * NG + g];
+        cy[r] = A.c[(1 * NC + k) * NG + g];
+        cp[r] = A.c[(2 * NC + k) * NG + g];
+        lx[r] = A.lam[(0 * NC + k) * NG + g];
+        ly[r] = A.lam[(1 * NC + k) * NG + g];
+        lp[r] = A.lam[(2 * NC + k) * NG + g];
+      }
+    }
+  }
+
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  f4 ux, uy, ep = zero;
+  float racc[4] = {0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  auto split = [&](const f4& v) -> bf8 {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) return split_b(v);
+    else return bf8{};
+  };
+  // one pass of the per-sample blocks at the current coefficients; returns u~
+  // (summed over the workgroup) and the lane's residual partials
+  auto heading = [&](f4& xd, f4& yd, f4& th, f4& W_, f4& E_) {
+    const bf8 cxb = split(cx), cyb = split(cy);
+    xd = eval<MODE>(O, 1, cx, cxb);
+    yd = eval<MODE>(O, 1, cy, cyb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool tv = gv && (TILE * w + 4 * q + r) < n;
+      th[r] = tv ? atan2f(yd[r], xd[r]) : 0.f;
+    }
+    W_ = contract<MODE>(O, 0, th, zero);
+    E_ = contract<MODE>(O, 0, ep, zero);
+    exchange(ex, buf, Wl, w, lane, W_, E_);
+    buf ^= 1;
+  };
+  auto project = [&](const f4& xd, const f4& yd, const f4& th) {
+    const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
+    const f4 x = eval<MODE>(O, 0, cx, cxb), y = eval<MODE>(O, 0, cy, cyb);
+    const f4 xdd = eval<MODE>(O, 2, cx, cxb), ydd = eval<MODE>(O, 2, cy, cyb);
+    const f4 psi = eval<MODE>(O, 0, cp, cpb);
+    SampleOut so;
+    samples(K, xi, box, w, lane, q, gv, x, y, xd, yd, xdd, ydd, psi, th, so);
+    ep = so.ep;
+    racc[0] = so.r_obs;
+    racc[1] = so.r_acc;
+    racc[2] = so.r_nh;
+    racc[3] = so.r_psi;
+    f4 ax = contract<MODE>(O, 0, so.sox, zero);
+    ax = contract<MODE>(O, 2, so.sax, ax);
+    ax = contract<MODE>(O, 1, so.ex, ax);
+    f4 ay = contract<MODE>(O, 0, so.soy, zero);
+    ay = contract<MODE>(O, 2, so.say, ay);
+    ay = contract<MODE>(O, 1, so.ey, ay);
+    exchange(ex, buf, Wl, w, lane, ax, ay);
+    buf ^= 1;
+    ux = ax;
+    uy = ay;
+  };
+  auto residuals = [&](f4& out) {
+    f4 rr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rr[k] = sum_rows(racc[k]);
+    f4 dummy = zero;
+    exchange(ex, buf, Wl, w, lane, rr, dummy);
+    buf ^= 1;
+    out = rr;
+  };
+
+  {
+    f4 xd, yd, th, W_, E_;
+    heading(xd, yd, th, W_, E_);
+    if (cold) cp = apply_psi<MODE>(O, c0p, rho * W_ + lp);
+    project(xd, yd, th);
+    ep = zero;  // the start has no pending heading multiplier step
+  }
+  int done = 0;
+  bool stopped = false;
+  for (int it = 0; it < A.iters; ++it) {
+    // x/y step (eq. 12 through eq. 18)
+    cx = apply_xy<MODE>(O, 0, c0xd, c0xf, cx, rho * ux + lx);
+    cy = apply_xy<MODE>(O, 1, c0yd, c0yf, cy, rho * uy + ly);
+    // pending heading multiplier (eq. 24) and heading step (eq. 13 through eq. 20)
+    f4 xd, yd, th, W_, E_;
+    heading(xd, yd, th, W_, E_);
+    lp = lp + rho * E_;
+    cp = apply_psi<MODE>(O, c0p, rho * W_ + lp);
+    // v, (alpha, d), (alpha_a, d_a) and u~ (eqs. 14-16, 21, 22)
+    project(xd, yd, th);
+    // multipliers of the x/y block (eq. 23)
+    lx = lx + rho * ux;
+    ly = ly + rho * uy;
+    done = it + 1;
+    if (A.tol > 0.f && done % 5 == 0) {
+      f4 rr;
+      residuals(rr);
+      // every goal of the group below tol (the group advances together)
+      const float worst = sqrtf(fmaxf(fmaxf(rr[0], rr[1]), rr[2]));
+      const bool ok = !gv || worst <= A.tol;
+      if (__ballot(!ok) == 0ull) {
+        stopped = true;
+      }
+      // the decision is identical in every wave (same totals), so the loop exits uniformly
+      if (stopped) break;
+    }
+  }
+  if (done > 0) {
+    f4 E_ = contract<MODE>(O, 0, ep, zero), dummy = zero;
+    exchange(ex, buf, Wl, w, lane, E_, dummy);
+    buf ^= 1;
+    lp = lp + rho * E_;
+  }
+  f4 rr;
+  residuals(rr);
+  if (w == 0 && gv) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        A.c[(0 * NC + k) * NG + g] = cx[r];
+        A.c[(1 * NC + k) * NG + g] = cy[r];
+        A.c[(2 * NC + k) * NG + g] = cp[r];
+        A.lam[(0 * NC + k) * NG + g] = lx[r];
+        A.lam[(1 * NC + k) * NG + g] = ly[r];
+        A.lam[(2 * NC + k) * NG + g] = lp[r];
+      }
+    }
+    if (q == 0) {
+      if (A.resid != nullptr)
+        for (int k = 0; k < 4; ++k) A.resid[k * NG + g] = sqrtf(rr[k]);
+      if (A.iters_out != nullptr) A.iters_out[g] = done;
+    }
+  }
+}
+
+}  // namespace
+
+size_t mfma_smem_bytes(int max_n, int max_m) {
+  const int W = (max_n + TILE - 1) / TILE;
+  const int mm = max_m > 0 ? max_m : 1;
+  return sizeof(float2) * (size_t)mm * TILE * W + sizeof(float4) * (size_t)W * mm +
+         sizeof(float4) * 2 * (size_t)W * 2 * WAVE;
+}
+
+hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream) {
+  if (a.n_goals <= 0) return hipSuccess;
+  if (G < 1 || G > GCOLS) return hipErrorInvalidValue;
+  const int W = (max_n + TILE - 1) / TILE;
+  const int blocks = (a.n_goals + G - 1) / G + a.n_scenes;
+  const size_t smem = mfma_smem_bytes(max_n, max_m);
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  const void* fn = mode == TRAJ_MODE_BF16X3 ? (const void*)k_am_mfma<TRAJ_MODE_BF16X3>
+                                            : (const void*)k_am_mfma<TRAJ_MODE_FP32>;
+  if (smem > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+  }
+  if (mode == TRAJ_MODE_BF16X3)
+    hipLaunchKernelGGL(k_am_mfma<TRAJ_MODE_BF16X3>, dim3(blocks), dim3(WAVE * W), smem, stream, a, G);
+  else
+    hipLaunchKernelGGL(k_am_mfma<TRAJ_MODE_FP32>, dim3(blocks), dim3(WAVE * W), smem, stream, a, G);
+  return hipGetLastError();
+}
+
+}  // namespace traj

@@ -19,7 +19,14 @@ LIB_PATH = os.path.join(_PKG, "libtraj.so")
 TRAJ_OK = 0
 TRAJ_INIT_COLD = 0x0
 TRAJ_INIT_FROM_STATE = 0x1
+TRAJ_PREC_FP32 = 0x0
+TRAJ_PREC_BF16X3 = 0x10
+TRAJ_KERNEL_AUTO = 0x0
+TRAJ_KERNEL_WAVE = 0x100
+TRAJ_KERNEL_MFMA = 0x200
 N_COEF = 11
+_KERNELS = {"auto": TRAJ_KERNEL_AUTO, "wave": TRAJ_KERNEL_WAVE, "mfma": TRAJ_KERNEL_MFMA}
+_PRECISIONS = {"fp32": TRAJ_PREC_FP32, "bf16x3": TRAJ_PREC_BF16X3}
 
 
 class Params(ctypes.Structure):
@@ -43,13 +50,17 @@ class StateC(ctypes.Structure):
                 ("iters", ctypes.c_void_p)]
 
 
+class TileC(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("group", ctypes.c_int32)]
+
+
 class MetaC(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("v_ref", ctypes.c_void_p), ("w1", ctypes.c_float),
                 ("w2", ctypes.c_float), ("y_rl", ctypes.c_void_p)]
 
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
-           "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce")
+           "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile")
 
 _lib = None
 
@@ -71,6 +82,8 @@ def lib():
     L.traj_debug_operators.argtypes = [vp, i32, vp, vp, vp]
     L.traj_debug_table_size.argtypes = [vp, i32]
     L.traj_debug_reduce.argtypes = [vp, vp, i32, vp]
+    L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
+    L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "traj_last_error" else ctypes.c_int
     _lib = L
@@ -181,12 +194,22 @@ class Solver:
             pass
 
     def solve(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,
-              from_state: bool = False, stream=None):
+              from_state: bool = False, precision: str = "fp32", kernel: str = "auto", stream=None):
         b = batch.c_struct()
         s = state.c_struct()
-        flags = TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD
+        flags = (TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD) | _PRECISIONS[precision] | _KERNELS[kernel]
         _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
                                       flags, _stream(stream)))
+
+    def set_tile(self, kernel: str, group: int = 16):
+        t = TileC(_KERNELS[kernel], int(group))
+        _check(lib().traj_set_tile(self.handle, ctypes.byref(t)))
+
+    def get_tile(self):
+        t = TileC()
+        _check(lib().traj_get_tile(self.handle, ctypes.byref(t)))
+        inv = {v: k for k, v in _KERNELS.items()}
+        return inv[t.kernel], t.group
 
     def score(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, kind=0, w1=1.0, w2=1.0,
               y_rl=None, stream=None):

@@ -31,15 +31,17 @@ def T():
     return traj
 
 
-def gpu_solve(T, batch, iters, init=None, tol=0.0, params=PARAMS, shapes=None):
+def gpu_solve(T, batch, iters, init=None, tol=0.0, params=PARAMS, shapes=None, kernel="auto", precision="fp32",
+              group=16):
     import torch
     solver = T.Solver(params, shapes or batch.shapes())
+    solver.set_tile("wave" if kernel == "auto" else kernel, group)
     db = T.DeviceBatch.from_batch(batch, shapes=shapes)
     st = T.DeviceState.empty(batch.n_goals)
     if init is not None:
         st.c.copy_(torch.from_numpy(init["c"]).cuda())
         st.lam.copy_(torch.from_numpy(init["lam"]).cuda())
-    solver.solve(db, st, iters, tol=tol, from_state=init is not None)
+    solver.solve(db, st, iters, tol=tol, from_state=init is not None, kernel=kernel, precision=precision)
     torch.cuda.synchronize()
     out = dict(c=st.c.cpu().numpy(), lam=st.lam.cpu().numpy(), resid=st.resid.cpu().numpy(),
                iters=st.iters.cpu().numpy())
