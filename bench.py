@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-goals", type=int, default=160)
-    ap.add_argument("--kernel", choices=["auto", "wave", "mfma"], default="auto",
+    ap.add_argument("--kernel", choices=["auto", "wave", "mfma", "group"], default="auto",
                     help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--group", type=int, default=None, help="goals per matrix-core workgroup")
@@ -105,17 +105,18 @@ def main():
     n, m, B = sc.n_time, sc.obs.shape[0], batch.n_goals
     solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
     kernel = args.kernel
+    persistent = True
     if kernel == "auto":
         from paper_2109_10392_amd import autotune
         tile = autotune.lookup(args.workload, args.precision)
-        kernel, group = (tile if tile is not None else ("wave", 16))
+        kernel, group, persistent = (tile if tile is not None else ("wave", 16, True))
     else:
         group = 16
     if args.group is not None:
         group = args.group
-    if args.precision == "bf16x3":
+    if args.precision == "bf16x3" and kernel == "wave":
         kernel = "mfma"
-    solver.set_tile(kernel, group)
+    solver.set_tile(kernel, group, persistent)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(B)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
@@ -170,7 +171,7 @@ def main():
                    {"workload": "uneven batch: 512 scenes, goals log-uniform 16-1024, obstacles U{4..64}, "
                                 "T in {50,100,150}, 100 AM iterations (cold start) + scoring",
                     "goals": B, "scenes": batch.n_scenes})
-        | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group},
+        | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group, "persistent": persistent},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]

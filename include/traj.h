@@ -45,6 +45,8 @@ extern "C" {
 #define TRAJ_KERNEL_AUTO 0x0u     /* kernel from the handle's tile setting (traj_set_tile)   */
 #define TRAJ_KERNEL_WAVE 0x100u   /* one wavefront per goal, lanes over time                 */
 #define TRAJ_KERNEL_MFMA 0x200u   /* matrix-core kernel: goal groups x 16-sample time tiles  */
+#define TRAJ_KERNEL_GROUP 0x400u  /* matrix-core kernel, one wavefront per goal group sweeping
+                                     its time tiles; cost-sorted work list (needs state.work) */
 
 #define TRAJ_N_COEF 11 /* Bernstein degree 10: coefficients per axis */
 
@@ -89,6 +91,9 @@ typedef struct {
   float *lam;     /* device [3][11][n_goals] */
   float *resid;   /* device [4][n_goals]: r_obs, r_acc, r_nh, r_psi after the last iteration (may be NULL) */
   int32_t *iters; /* device [n_goals]: iterations performed (may be NULL) */
+  int32_t *work;  /* device scratch of work_ints int32 for TRAJ_KERNEL_GROUP (the work list and
+                     its claim counter; contents are overwritten by every solve), else may be NULL */
+  int64_t work_ints;
 } traj_state;
 
 /* Meta-cost of Sec. III-F. */
@@ -120,11 +125,15 @@ int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes
  * variables (eq. 22 and the clipped 1-D minimiser of eq. 15), acceleration polar
  * variables (eq. 16), multipliers (eqs. 23-24).
  *   flags: TRAJ_INIT_COLD or TRAJ_INIT_FROM_STATE, | TRAJ_PREC_FP32 or
- *          TRAJ_PREC_BF16X3, | TRAJ_KERNEL_AUTO, TRAJ_KERNEL_WAVE or
- *          TRAJ_KERNEL_MFMA (BF16X3 always runs on the matrix-core kernel).
+ *          TRAJ_PREC_BF16X3, | TRAJ_KERNEL_AUTO, TRAJ_KERNEL_WAVE,
+ *          TRAJ_KERNEL_MFMA or TRAJ_KERNEL_GROUP (BF16X3 runs on a matrix-core
+ *          kernel: the group kernel if asked for, else the MFMA kernel).
  *   tol: <= 0 runs exactly `iters` iterations; > 0 stops at the first multiple
  *        of 5 iterations where max(r_obs, r_acc, r_nh) <= tol: per goal in the
- *        wave kernel, per goal group (all of its goals) in the matrix-core kernel.
+ *        wave kernel, per goal group (all of its goals) in the matrix-core kernels.
+ *   The group kernel needs state->work with at least traj_work_ints(...) entries
+ *   (TRAJ_E_INVAL otherwise). Two solves that share a work buffer must not run
+ *   concurrently.
  *   iters: 0 <= iters <= 100000. n_goals == 0 is a no-op.
  * Shape mismatches found on the device (unknown shape id, wrong obstacle count)
  * set that scene's residuals to NaN; nothing aborts.
@@ -145,12 +154,16 @@ int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, i
 int traj_score(void *handle, const traj_batch *batch, const traj_state *state, const traj_metacost *mc,
                float *cost, int32_t *best, void *stream);
 
-/* Kernel tile of a handle. kernel: TRAJ_KERNEL_WAVE or TRAJ_KERNEL_MFMA; group:
- * goals per matrix-core workgroup, 1..16 (the MFMA has 16 goal columns; fewer
- * goals per group spread a small batch over more compute units). */
+/* Kernel tile of a handle. kernel: TRAJ_KERNEL_WAVE, TRAJ_KERNEL_MFMA or
+ * TRAJ_KERNEL_GROUP; group: goals per matrix-core goal group, 1..16 (the MFMA
+ * has 16 goal columns; fewer goals per group spread a small batch over more
+ * compute units); persistent (group kernel): 1 = a device-filling grid whose
+ * wavefronts claim goal groups from the work list until it is exhausted, 0 = one
+ * wavefront per listed group. */
 typedef struct {
   int32_t kernel;
   int32_t group;
+  int32_t persistent;
 } traj_tile;
 
 /*
@@ -161,6 +174,15 @@ typedef struct {
  */
 int traj_set_tile(void *handle, const traj_tile *tile);
 int traj_get_tile(void *handle, traj_tile *tile);
+
+/*
+ * traj_work_ints -- entries of the int32 device scratch (traj_state.work) that a
+ * group-kernel solve of a batch with n_scenes scenes and n_goals goals needs with
+ * the handle's current group size: 4 + 2 (ceil(n_goals / group) + n_scenes). The
+ * wave and MFMA kernels do not use the scratch. Host-only.
+ * Errors: TRAJ_E_INVAL (NULL handle or out, negative sizes).
+ */
+int traj_work_ints(void *handle, int n_scenes, int n_goals, int64_t *out);
 
 /* traj_destroy -- free the handle's device memory. NULL is a no-op. */
 int traj_destroy(void *handle);

@@ -1,10 +1,12 @@
 """Tile autotuner: time the solver's kernel tiles on a workload, keep the fastest.
 
-A tile is (kernel, group): the one-wave-per-goal kernel, or the matrix-core
-kernel with `group` goals per workgroup (1..16 MFMA columns used). The result
-is stored per (workload, precision) in tuning.json next to this file and read
-back by `lookup`, which the benchmark and the binding use for
-TRAJ_KERNEL_AUTO.
+A tile is (kernel, group, persistent): the one-wave-per-goal kernel; the
+matrix-core kernel with `group` goals per workgroup (1..16 MFMA columns used)
+and one wave per 16-sample time tile; or the group kernel, one wave per goal
+group sweeping its own time tiles over a cost-sorted work list, consumed by a
+persistent grid or one wave per listed group. The result is stored per
+(workload, precision) in tuning.json next to this file and read back by
+`lookup`, which the benchmark uses for TRAJ_KERNEL_AUTO.
 """
 from __future__ import annotations
 
@@ -13,7 +15,8 @@ import os
 
 TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
-CANDIDATES = [("wave", 16), ("mfma", 16), ("mfma", 8), ("mfma", 4), ("mfma", 2)]
+CANDIDATES = [("wave", 16, True), ("mfma", 16, True), ("mfma", 4, True), ("group", 16, True), ("group", 16, False),
+              ("group", 8, True), ("group", 4, True), ("group", 4, False)]
 
 
 def lookup(workload: str, precision: str = "fp32"):
@@ -22,17 +25,19 @@ def lookup(workload: str, precision: str = "fp32"):
     with open(TUNING_PATH) as f:
         table = json.load(f)
     entry = table.get(f"{workload}/{precision}")
-    return None if entry is None else (entry["kernel"], int(entry["group"]))
+    if entry is None:
+        return None
+    return entry["kernel"], int(entry["group"]), bool(entry.get("persistent", True))
 
 
 def tune(solver, db, st, iters, precision="fp32", candidates=None, reps=3):
-    """Return [(ms, kernel, group)] sorted fastest first for this batch."""
+    """Return [(ms, kernel, group, persistent)] sorted fastest first for this batch."""
     import torch
     res = []
-    for kernel, group in (candidates or CANDIDATES):
+    for kernel, group, persistent in (candidates or CANDIDATES):
         if precision == "bf16x3" and kernel == "wave":
             continue
-        solver.set_tile(kernel, group)
+        solver.set_tile(kernel, group, persistent)
         solver.solve(db, st, iters, precision=precision)  # warm-up
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -41,18 +46,21 @@ def tune(solver, db, st, iters, precision="fp32", candidates=None, reps=3):
             solver.solve(db, st, iters, precision=precision)
         b.record()
         torch.cuda.synchronize()
-        res.append((a.elapsed_time(b) / reps, kernel, group))
+        res.append((a.elapsed_time(b) / reps, kernel, group, persistent))
+        print(f"  {kernel:5s} group {group:2d} persistent {int(persistent)}: {res[-1][0]:8.3f} ms", flush=True)
     res.sort()
     return res
 
 
-def store(workload: str, precision: str, kernel: str, group: int, ms: float, sweep):
+def store(workload: str, precision: str, sweep):
     table = {}
     if os.path.exists(TUNING_PATH):
         with open(TUNING_PATH) as f:
             table = json.load(f)
-    table[f"{workload}/{precision}"] = {"kernel": kernel, "group": group, "ms": ms,
-                                         "sweep": [{"ms": t, "kernel": k, "group": g} for t, k, g in sweep]}
+    ms, kernel, group, persistent = sweep[0]
+    table[f"{workload}/{precision}"] = {"kernel": kernel, "group": group, "persistent": persistent, "ms": ms,
+                                         "sweep": [{"ms": t, "kernel": k, "group": g, "persistent": p}
+                                                   for t, k, g, p in sweep]}
     with open(TUNING_PATH, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
 
@@ -77,12 +85,11 @@ def main():
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
     sweep = tune(solver, db, st, args.iters, args.precision)
-    for ms, k, g in sweep:
-        print(f"{args.workload}/{args.precision} {k:5s} group {g:2d}: {ms:8.3f} ms", flush=True)
+    for ms, k, g, p in sweep:
+        print(f"{args.workload}/{args.precision} {k:5s} group {g:2d} persistent {int(p)}: {ms:8.3f} ms", flush=True)
     if args.write:
-        ms, k, g = sweep[0]
-        store(args.workload, args.precision, k, g, ms, sweep)
-        print(f"stored {k} group {g} in {TUNING_PATH}", flush=True)
+        store(args.workload, args.precision, sweep)
+        print(f"stored {sweep[0][1:]} in {TUNING_PATH}", flush=True)
     solver.close()
 
 

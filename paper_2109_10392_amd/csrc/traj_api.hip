@@ -43,7 +43,8 @@ struct Handle {
   double* d_tables64 = nullptr;
   int max_n = 0, max_m = 0;
   size_t table_floats = 0;
-  traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16};
+  traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16, 1};
+  int resident_blocks[2] = {0, 0};  // group kernel workgroups resident at once, per precision mode
 };
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
@@ -129,6 +130,20 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
     traj_destroy(h);
     return hip_fail(e, "traj_setup");
   }
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+    traj_destroy(h);
+    return hip_fail(e, "traj_setup: device query");
+  }
+  for (int mode = 0; mode < 2; ++mode) {
+    int per_cu = 0;
+    if ((e = traj::group_blocks_per_cu(mode, &per_cu)) != hipSuccess) {
+      traj_destroy(h);
+      return hip_fail(e, "traj_setup: occupancy query");
+    }
+    h->resident_blocks[mode] = cus * (per_cu > 0 ? per_cu : 1);
+  }
   *handle_out = h;
   return TRAJ_OK;
 }
@@ -153,14 +168,24 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   if (state == nullptr) return fail(TRAJ_E_INVAL, "state is NULL");
   if (iters < 0 || iters > 100000) return fail(TRAJ_E_INVAL, "iters must be in [0, 100000]");
   if (!isfinite(tol)) return fail(TRAJ_E_INVAL, "tol must be finite");
-  const uint32_t known = TRAJ_INIT_FROM_STATE | TRAJ_PREC_BF16X3 | TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA;
+  const uint32_t kernels = TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA | TRAJ_KERNEL_GROUP;
+  const uint32_t known = TRAJ_INIT_FROM_STATE | TRAJ_PREC_BF16X3 | kernels;
   if ((flags & ~known) != 0) return fail(TRAJ_E_INVAL, "unknown flags 0x%x", flags);
-  if ((flags & TRAJ_KERNEL_WAVE) && (flags & TRAJ_KERNEL_MFMA))
-    return fail(TRAJ_E_INVAL, "TRAJ_KERNEL_WAVE and TRAJ_KERNEL_MFMA are exclusive");
-  if ((flags & TRAJ_PREC_BF16X3) && (flags & TRAJ_KERNEL_WAVE))
-    return fail(TRAJ_E_INVAL, "TRAJ_PREC_BF16X3 runs on the matrix-core kernel only");
+  uint32_t kernel = flags & kernels;
+  if (kernel != 0 && (kernel & (kernel - 1)) != 0)
+    return fail(TRAJ_E_INVAL, "TRAJ_KERNEL_WAVE, TRAJ_KERNEL_MFMA and TRAJ_KERNEL_GROUP are exclusive");
+  if ((flags & TRAJ_PREC_BF16X3) && kernel == TRAJ_KERNEL_WAVE)
+    return fail(TRAJ_E_INVAL, "TRAJ_PREC_BF16X3 runs on a matrix-core kernel only");
+  if (kernel == 0) kernel = (uint32_t)h->tile.kernel;
+  if ((flags & TRAJ_PREC_BF16X3) && kernel == TRAJ_KERNEL_WAVE) kernel = TRAJ_KERNEL_MFMA;
   if (batch->n_goals == 0) return TRAJ_OK;
   if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
+  if (kernel == TRAJ_KERNEL_GROUP) {
+    const int64_t need = traj::group_work_ints(batch->n_scenes, batch->n_goals, h->tile.group);
+    if (state->work == nullptr || state->work_ints < need)
+      return fail(TRAJ_E_INVAL, "the group kernel needs state.work with %lld int32 (got %lld)", (long long)need,
+                  (long long)(state->work == nullptr ? 0 : state->work_ints));
+  }
   traj::SolveArgs a;
   a.goal_off = batch->goal_off;
   a.obs_off = batch->obs_off;
@@ -182,11 +207,12 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   a.flags = (int)flags;
   a.tol = tol;
   a.k = consts(h->p);
-  bool mfma = (flags & TRAJ_PREC_BF16X3) || (flags & TRAJ_KERNEL_MFMA) ||
-              (!(flags & TRAJ_KERNEL_WAVE) && h->tile.kernel == (int32_t)TRAJ_KERNEL_MFMA);
+  const int mode = (flags & TRAJ_PREC_BF16X3) ? traj::TRAJ_MODE_BF16X3 : traj::TRAJ_MODE_FP32;
   hipError_t e;
-  if (mfma) {
-    const int mode = (flags & TRAJ_PREC_BF16X3) ? traj::TRAJ_MODE_BF16X3 : traj::TRAJ_MODE_FP32;
+  if (kernel == TRAJ_KERNEL_GROUP) {
+    e = traj::launch_solve_group(a, mode, h->tile.group, h->tile.persistent != 0, h->resident_blocks[mode],
+                                 state->work, (hipStream_t)stream);
+  } else if (kernel == TRAJ_KERNEL_MFMA) {
     e = traj::launch_solve_mfma(a, mode, h->tile.group, h->max_n, h->max_m, (hipStream_t)stream);
   } else {
     e = traj::launch_solve(a, h->max_n, h->max_m, (hipStream_t)stream);
@@ -236,9 +262,11 @@ int traj_set_tile(void* handle, const traj_tile* tile) {
   g_err.clear();
   Handle* h = (Handle*)handle;
   if (h == nullptr || tile == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
-  if (tile->kernel != (int32_t)TRAJ_KERNEL_WAVE && tile->kernel != (int32_t)TRAJ_KERNEL_MFMA)
+  if (tile->kernel != (int32_t)TRAJ_KERNEL_WAVE && tile->kernel != (int32_t)TRAJ_KERNEL_MFMA &&
+      tile->kernel != (int32_t)TRAJ_KERNEL_GROUP)
     return fail(TRAJ_E_INVAL, "unknown kernel 0x%x", (unsigned)tile->kernel);
   if (tile->group < 1 || tile->group > 16) return fail(TRAJ_E_INVAL, "group must be in [1, 16]");
+  if (tile->persistent != 0 && tile->persistent != 1) return fail(TRAJ_E_INVAL, "persistent must be 0 or 1");
   h->tile = *tile;
   return TRAJ_OK;
 }
@@ -248,6 +276,15 @@ int traj_get_tile(void* handle, traj_tile* tile) {
   Handle* h = (Handle*)handle;
   if (h == nullptr || tile == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
   *tile = h->tile;
+  return TRAJ_OK;
+}
+
+int traj_work_ints(void* handle, int n_scenes, int n_goals, int64_t* out) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr || out == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
+  if (n_scenes < 0 || n_goals < 0) return fail(TRAJ_E_INVAL, "negative batch size");
+  *out = traj::group_work_ints(n_scenes, n_goals, h->tile.group);
   return TRAJ_OK;
 }
 

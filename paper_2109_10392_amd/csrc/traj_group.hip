@@ -1,0 +1,463 @@
+// Batched alternating minimisation (Algorithm 1, Sec. III-D) on the matrix
+// cores, one wavefront per goal group.
+//
+// A wavefront owns up to 16 goals of one scene (the MFMA columns) and sweeps the
+// time axis itself in 16-sample tiles, so no partial sum ever leaves the wave and
+// there is no barrier in the iteration. Per iteration:
+//   x/y step (eqs. 17-18)       c = MG c + M (rho u~ + lambda) + M_b b     f64 MFMA apply
+//   heading sweep               per tile: x', y' (MFMA), theta = atan2, W += P^T theta
+//   heading step (eqs. 19-20)   c_psi = M_psi (rho W + lambda_psi) + M_bpsi b_psi
+//   projection sweep            per tile: x, y, x', y', x'', y'', psi (MFMA), the
+//                               closed forms of eqs. 21, 22, 15, 16 (vector ALU),
+//                               u~ += P^T s_o + P''^T s_a + P'^T (z - x') and
+//                               E += P^T (theta - psi) (MFMA)
+//   multipliers (eqs. 23, 24)   lambda += rho u~, lambda_psi += rho E
+// The algebra is that of the other two kernels (reduced F^T g, increments
+// contracted from per-sample residuals). A tile's basis operands are read from
+// the packed per-shape table: one coalesced float4 per lane and matrix.
+//
+// Uneven batches. The goal groups of a batch are listed by a one-workgroup list
+// kernel in decreasing order of cost (16-sample tiles x (32 + obstacles)). The
+// solver grid either takes them in list order, one per wavefront, or runs
+// persistently: a grid that fits on the device at once, each wavefront claiming
+// the next group from an atomic counter until the list is exhausted. Either way
+// the most expensive groups start first and the cheapest fill the tail.
+#include "traj_mma.h"
+
+namespace traj {
+namespace {
+
+using namespace dev;
+using namespace mma;
+
+constexpr int GROUP_WAVES = 4;      // independent wavefronts per workgroup
+constexpr int LIST_THREADS = 1024;  // list kernel: one workgroup
+constexpr int COST_BUCKETS = 2048;  // cost keys n_tiles * (32 + m) <= 12 * 96
+
+struct GroupArgs {
+  int32_t* header;   // [0] claim counter, [1] groups listed
+  int2* items;        // (scene, first goal) of each group, decreasing cost
+  int capacity;       // entries of items
+  int G;              // goals per group, 1..16
+  int persistent;
+};
+
+__device__ __forceinline__ int group_cost(const SolveArgs& A, int scene) {
+  const int sid = A.shape_id[scene];
+  if (sid < 0 || sid >= A.n_shapes) return 0;
+  const ShapeDesc sd = A.shapes[sid];
+  const int n = min(max(sd.n, 0), MAX_TIME), m = min(max(sd.m, 0), MAX_OBS);
+  return n_tiles(n) * (32 + m);
+}
+
+__device__ __forceinline__ void scene_goals(const SolveArgs& A, int s, int& g0, int& g1) {
+  g0 = min(max((int)A.goal_off[s], 0), A.n_goals);
+  g1 = min(max((int)A.goal_off[s + 1], g0), A.n_goals);
+}
+
+// Counting sort of the goal groups by decreasing cost; resets the claim counter.
+// The order among groups of equal cost is unspecified (it does not change any
+// result: the groups are independent).
+__global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L) {
+  __shared__ int hist[COST_BUCKETS];
+  __shared__ int part[LIST_THREADS / WAVE];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < COST_BUCKETS; b += LIST_THREADS) hist[b] = 0;
+  __syncthreads();
+  for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
+    int g0, g1;
+    scene_goals(A, s, g0, g1);
+    const int cnt = (g1 - g0 + L.G - 1) / L.G;
+    if (cnt > 0) atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
+  }
+  __syncthreads();
+  // exclusive scan in decreasing key order: thread t owns keys 2t+1, 2t (descending
+  // rank r = COST_BUCKETS - 1 - key)
+  const int lane = tid & (WAVE - 1), wv = tid >> 6;
+  const int k_hi = COST_BUCKETS - 1 - 2 * tid, k_lo = k_hi - 1;
+  const int a = hist[k_hi], b = hist[k_lo];
+  int incl = a + b;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int y = __shfl_up(incl, d, WAVE);
+    if (lane >= d) incl += y;
+  }
+  if (lane == WAVE - 1) part[wv] = incl;
+  __syncthreads();
+  int pre = 0, total = 0;
+  for (int w = 0; w < LIST_THREADS / WAVE; ++w) {
+    if (w < wv) pre += part[w];
+    total += part[w];
+  }
+  const int excl = pre + incl - (a + b);
+  __syncthreads();
+  hist[k_hi] = excl;  // becomes the cursor of each bucket
+  hist[k_lo] = excl + a;
+  __syncthreads();
+  for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
+    int g0, g1;
+    scene_goals(A, s, g0, g1);
+    const int cnt = (g1 - g0 + L.G - 1) / L.G;
+    if (cnt <= 0) continue;
+    int pos = atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
+    for (int i = 0; i < cnt && pos < L.capacity; ++i, ++pos)
+      L.items[pos] = make_int2(s, g0 + i * L.G);
+  }
+  if (tid == 0) {
+    L.header[0] = 0;
+    L.header[1] = min(total, L.capacity);
+  }
+}
+
+struct GConsts {
+  int n, m, nt;
+  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2, dt;
+};
+
+template <int MODE>
+__device__ __forceinline__ void tile_operand(Operand<MODE>& o, const float4* __restrict__ pk, int w, int s, int lane) {
+  const float4 v = pk[(w * PACK_SLOTS + s) * WAVE + lane];
+  const float a[4] = {v.x, v.y, v.z, v.w};
+  make_operand<MODE>(o, a);
+}
+
+struct TileOut {
+  f4 sox, soy, sax, say, ex, ey, ep;
+};
+
+// Per-sample closed forms at the lane's 4 samples of tile w (eqs. 21, 22, 15, 16)
+// and the residual partials. Obstacle predictions (constant velocity) are
+// evaluated where needed; only obstacles whose box over the tile's time span,
+// inflated by the scaled half-axes plus 0.1%, meets the box of the tile's
+// trajectory samples are visited: for every other pair the scaled distance
+// exceeds 1 in FP32 too, so the result is that of visiting all obstacles.
+__device__ __forceinline__ void tile_samples(const GConsts& K, const float4* __restrict__ obs, int w, int lane, int q,
+                                             bool gv, const f4& x, const f4& y, const f4& xd, const f4& yd,
+                                             const f4& xdd, const f4& ydd, const f4& psi, const f4& th, TileOut& o,
+                                             float (&racc)[4]) {
+  bool tv[4];
+  float X[4], Y[4], Tm[4];
+  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = TILE * w + 4 * q + r;
+    tv[r] = gv && i < K.n;
+    Tm[r] = (float)i * K.dt;
+    X[r] = x[r] * K.inv_a;
+    Y[r] = y[r] * K.inv_b;
+    if (tv[r]) {
+      lxlo = fminf(lxlo, X[r]);
+      lxhi = fmaxf(lxhi, X[r]);
+      lylo = fminf(lylo, Y[r]);
+      lyhi = fmaxf(lyhi, Y[r]);
+    }
+    // velocity (eq. 21), heading direction, z - x'
+    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
+    float sn, cs;
+    sincos_heading(psi[r], &sn, &cs);
+    const float ex = fmaf(v, cs, -xd[r]), ey = fmaf(v, sn, -yd[r]);
+    // acceleration polar variables (eq. 16): d_a = min(a_max, h), s_a = (x'', y'') (d_a / h - 1)
+    const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
+    const float fa = h2 > K.amax2 ? K.amax * rsqrtf(h2) - 1.f : 0.f;
+    const float sax = xdd[r] * fa, say = ydd[r] * fa;
+    const float ep = th[r] - psi[r];
+    o.ex[r] = tv[r] ? ex : 0.f;
+    o.ey[r] = tv[r] ? ey : 0.f;
+    o.sax[r] = tv[r] ? sax : 0.f;
+    o.say[r] = tv[r] ? say : 0.f;
+    o.ep[r] = tv[r] ? ep : 0.f;
+    if (tv[r]) {
+      racc[1] = fmaf(sax, sax, fmaf(say, say, racc[1]));
+      racc[2] = fmaf(ex, ex, fmaf(ey, ey, racc[2]));
+      racc[3] = fmaf(ep, ep, racc[3]);
+    }
+  }
+  // obstacle polar variables (eqs. 15, 22) in units scaled by (1/a, 1/b):
+  // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse
+  const float xlo = wave_min(lxlo), xhi = wave_max(lxhi), ylo = wave_min(lylo), yhi = wave_max(lyhi);
+  bool hit = false;
+  if (lane < K.m) {
+    const float4 ob = obs[lane];
+    const int i0 = min(TILE * w, K.n - 1), i1 = min(TILE * w + TILE - 1, K.n - 1);
+    const float t0 = (float)i0 * K.dt, t1 = (float)i1 * K.dt;
+    const float xa = fmaf(ob.z, t0, ob.x) * K.inv_a, xb = fmaf(ob.z, t1, ob.x) * K.inv_a;
+    const float ya = fmaf(ob.w, t0, ob.y) * K.inv_b, yb = fmaf(ob.w, t1, ob.y) * K.inv_b;
+    constexpr float R = 1.001f;
+    hit = (xhi > fminf(xa, xb) - R) && (xlo < fmaxf(xa, xb) + R) && (yhi > fminf(ya, yb) - R) &&
+          (ylo < fmaxf(ya, yb) + R);
+  }
+  unsigned long long cand = __ballot(hit);
+  float Sx[4] = {0.f, 0.f, 0.f, 0.f}, Sy[4] = {0.f, 0.f, 0.f, 0.f};
+  while (cand) {
+    const int jo = __builtin_ctzll(cand);
+    cand &= cand - 1;
+    const float4 ob = obs[jo];
+    float tx[4], ty[4], qq[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tx[r] = X[r] - fmaf(ob.z, Tm[r], ob.x) * K.inv_a;
+      ty[r] = Y[r] - fmaf(ob.w, Tm[r], ob.y) * K.inv_b;
+      qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
+    }
+    if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (qq[r] < 1.f) {
+          if (qq[r] > 0.f) {
+            const float f = rsqrtf(qq[r]) - 1.f;
+            Sx[r] = fmaf(tx[r], f, Sx[r]);
+            Sy[r] = fmaf(ty[r], f, Sy[r]);
+            racc[0] = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, racc[0]);
+          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
+            Sx[r] += 1.f;
+            racc[0] += K.a2;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    o.sox[r] = K.a * Sx[r];
+    o.soy[r] = K.b * Sy[r];
+  }
+}
+
+template <int MODE>
+__device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int lane) {
+  const int j = lane & 15, q = lane >> 4;
+  const int NG = A.n_goals;
+  int s0, s1;
+  scene_goals(A, scene, s0, s1);
+  const int gcount = min(G, s1 - g0);
+  if (gcount <= 0) return;
+  const bool gv = j < gcount;
+  const int g = g0 + (gv ? j : 0);
+  const int sid = A.shape_id[scene];
+  const int o0 = A.obs_off[scene];
+  const int m_scene = A.obs_off[scene + 1] - o0;
+  bool bad = sid < 0 || sid >= A.n_shapes;
+  ShapeDesc sd = {};
+  if (!bad) sd = A.shapes[sid];
+  bad = bad || m_scene != sd.m || sd.n < NC || sd.n > MAX_TIME;
+  if (bad) {
+    if (gv && q == 0) {
+      if (A.resid != nullptr)
+        for (int k = 0; k < 4; ++k) A.resid[k * NG + g] = __builtin_nanf("");
+      if (A.iters_out != nullptr) A.iters_out[g] = 0;
+    }
+    return;
+  }
+  GConsts K;
+  K.n = sd.n;
+  K.m = sd.m;
+  K.nt = n_tiles(sd.n);
+  K.dt = sd.t_f / (float)(sd.n - 1);
+  K.rho = A.k.rho;
+  K.a = A.k.a;
+  K.b = A.k.b;
+  K.inv_a = 1.f / K.a;
+  K.inv_b = 1.f / K.b;
+  K.a2 = K.a * K.a;
+  K.b2 = K.b * K.b;
+  K.vmin = A.k.v_min;
+  K.vmax = A.k.v_max;
+  K.amax = A.k.a_max;
+  K.amax2 = K.amax * K.amax;
+  const int n = K.n;
+  const float rho = K.rho;
+  const float* T = A.tables + sd.table_off;
+  const double* T64 = A.tables64 + sd.table64_off;
+  const float4* pk = reinterpret_cast<const float4*>(T + tab_pack(n));
+  const float4* obs = reinterpret_cast<const float4*>(A.obs) + o0;
+
+  ApplyOps<MODE> ap;
+  load_apply_ops<MODE>(ap, T, T64, n, j, q);
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  f4 cx = zero, cy = zero, cp = zero, lx = zero, ly = zero, lp = zero;
+  const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
+  Particular P;
+  particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, cold, cx, cy);
+  if (!cold) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        cx[r] = A.c[(0 * NC + k) * NG + g];
+        cy[r] = A.c[(1 * NC + k) * NG + g];
+        cp[r] = A.c[(2 * NC + k) * NG + g];
+        lx[r] = A.lam[(0 * NC + k) * NG + g];
+        ly[r] = A.lam[(1 * NC + k) * NG + g];
+        lp[r] = A.lam[(2 * NC + k) * NG + g];
+      }
+    }
+  }
+
+  auto split = [&](const f4& v) -> bf8 {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) return split_b(v);
+    else return bf8{};
+  };
+  // heading input: W = P^T theta, theta = atan2(y', x') at every sample
+  auto heading_sweep = [&]() -> f4 {
+    const bf8 cxb = split(cx), cyb = split(cy);
+    f4 W = zero;
+    for (int w = 0; w < K.nt; ++w) {
+      Operand<MODE> evd, ctp;
+      tile_operand<MODE>(evd, pk, w, 1, lane);
+      tile_operand<MODE>(ctp, pk, w, 3, lane);
+      const f4 xd = eval<MODE>(evd, cx, cxb), yd = eval<MODE>(evd, cy, cyb);
+      f4 th;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2f(yd[r], xd[r]) : 0.f;
+      W = contract<MODE>(ctp, th, W);
+    }
+    return W;
+  };
+  // projections at (cx, cy, cp): u~ per axis, E = P^T (theta - psi) and the
+  // lane's squared residual partials (r_obs, r_acc, r_nh, r_psi)
+  float racc[4];
+  auto projection_sweep = [&](f4& ux, f4& uy, f4& E) {
+    const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
+    ux = zero;
+    uy = zero;
+    E = zero;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) racc[k] = 0.f;
+    for (int w = 0; w < K.nt; ++w) {
+      Operand<MODE> ev0, ev1, ev2;
+      tile_operand<MODE>(ev0, pk, w, 0, lane);
+      tile_operand<MODE>(ev1, pk, w, 1, lane);
+      tile_operand<MODE>(ev2, pk, w, 2, lane);
+      const f4 x = eval<MODE>(ev0, cx, cxb), y = eval<MODE>(ev0, cy, cyb), psi = eval<MODE>(ev0, cp, cpb);
+      const f4 xd = eval<MODE>(ev1, cx, cxb), yd = eval<MODE>(ev1, cy, cyb);
+      const f4 xdd = eval<MODE>(ev2, cx, cxb), ydd = eval<MODE>(ev2, cy, cyb);
+      f4 th;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2f(yd[r], xd[r]) : 0.f;
+      TileOut o;
+      tile_samples(K, obs, w, lane, q, gv, x, y, xd, yd, xdd, ydd, psi, th, o, racc);
+      Operand<MODE> ct0, ct1, ct2;
+      tile_operand<MODE>(ct0, pk, w, 3, lane);
+      tile_operand<MODE>(ct1, pk, w, 4, lane);
+      tile_operand<MODE>(ct2, pk, w, 5, lane);
+      ux = contract<MODE>(ct0, o.sox, ux);
+      ux = contract<MODE>(ct2, o.sax, ux);
+      ux = contract<MODE>(ct1, o.ex, ux);
+      uy = contract<MODE>(ct0, o.soy, uy);
+      uy = contract<MODE>(ct2, o.say, uy);
+      uy = contract<MODE>(ct1, o.ey, uy);
+      E = contract<MODE>(ct0, o.ep, E);
+    }
+  };
+
+  f4 ux, uy, E;
+  {
+    // split variables of the starting point: heading QP (cold start only), v,
+    // (alpha, d), (alpha_a, d_a); no multiplier is updated here
+    const f4 W = heading_sweep();
+    if (cold) cp = apply_psi<MODE>(ap, P.c0p, rho * W + lp);
+    projection_sweep(ux, uy, E);
+  }
+  int done = 0;
+  for (int it = 0; it < A.iters; ++it) {
+    // x/y step (eq. 12 through eq. 18)
+    cx = apply_xy<MODE>(ap, 0, P.c0xd, P.c0xf, cx, rho * ux + lx);
+    cy = apply_xy<MODE>(ap, 1, P.c0yd, P.c0yf, cy, rho * uy + ly);
+    // heading step (eq. 13 through eq. 20)
+    const f4 W = heading_sweep();
+    cp = apply_psi<MODE>(ap, P.c0p, rho * W + lp);
+    // v, (alpha, d), (alpha_a, d_a), then the multipliers (eqs. 23, 24)
+    projection_sweep(ux, uy, E);
+    lx = lx + rho * ux;
+    ly = ly + rho * uy;
+    lp = lp + rho * E;
+    done = it + 1;
+    if (A.tol > 0.f && done % 5 == 0) {
+      // every goal of the group at or below tol (the group advances together)
+      const float worst = sqrtf(fmaxf(fmaxf(sum_rows(racc[0]), sum_rows(racc[1])), sum_rows(racc[2])));
+      if (__ballot(gv && !(worst <= A.tol)) == 0ull) break;
+    }
+  }
+  float rr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rr[k] = sum_rows(racc[k]);
+  if (gv) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        A.c[(0 * NC + k) * NG + g] = cx[r];
+        A.c[(1 * NC + k) * NG + g] = cy[r];
+        A.c[(2 * NC + k) * NG + g] = cp[r];
+        A.lam[(0 * NC + k) * NG + g] = lx[r];
+        A.lam[(1 * NC + k) * NG + g] = ly[r];
+        A.lam[(2 * NC + k) * NG + g] = lp[r];
+      }
+    }
+    if (q == 0) {
+      if (A.resid != nullptr)
+        for (int k = 0; k < 4; ++k) A.resid[k * NG + g] = sqrtf(rr[k]);
+      if (A.iters_out != nullptr) A.iters_out[g] = done;
+    }
+  }
+}
+
+__device__ __forceinline__ int claim(int32_t* header) {
+  int v = 0;
+  if ((threadIdx.x & (WAVE - 1)) == 0) v = atomicAdd(header, 1);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(WAVE * GROUP_WAVES) void k_am_group(SolveArgs A, GroupArgs L) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+  const int n_items = L.header[1];
+  int idx = L.persistent ? claim(L.header) : (int)blockIdx.x * GROUP_WAVES + wv;
+  // every wavefront leaves once the list is exhausted: the counter only grows
+  while (idx < n_items) {
+    const int2 it = L.items[idx];
+    solve_group<MODE>(A, L.G, it.x, it.y, lane);
+    idx = L.persistent ? claim(L.header) : n_items;
+  }
+}
+
+}  // namespace
+
+int64_t group_work_ints(int n_scenes, int n_goals, int G) {
+  if (G < 1) G = 1;
+  // header (4) + (scene, first goal) per group; sum_s ceil(goals_s / G) <= goals / G + scenes
+  return 4 + 2 * ((int64_t)(n_goals + G - 1) / G + (int64_t)n_scenes);
+}
+
+hipError_t group_blocks_per_cu(int mode, int* blocks) {
+  const void* fn = mode == TRAJ_MODE_BF16X3 ? (const void*)k_am_group<TRAJ_MODE_BF16X3>
+                                            : (const void*)k_am_group<TRAJ_MODE_FP32>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, WAVE * GROUP_WAVES, 0);
+}
+
+hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
+                              int32_t* work, hipStream_t stream) {
+  if (a.n_goals <= 0) return hipSuccess;
+  if (G < 1 || G > GCOLS || work == nullptr) return hipErrorInvalidValue;
+  const int64_t cap64 = (group_work_ints(a.n_scenes, a.n_goals, G) - 4) / 2;
+  if (cap64 > (int64_t)1 << 30) return hipErrorInvalidValue;
+  GroupArgs L;
+  L.header = work;
+  L.items = reinterpret_cast<int2*>(work + 4);
+  L.capacity = (int)cap64;
+  L.G = G;
+  L.persistent = persistent ? 1 : 0;
+  hipLaunchKernelGGL(k_list, dim3(1), dim3(LIST_THREADS), 0, stream, a, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (cap64 + GROUP_WAVES - 1) / GROUP_WAVES;
+  if (persistent && resident_blocks > 0 && blocks > resident_blocks) blocks = resident_blocks;
+  if (mode == TRAJ_MODE_BF16X3)
+    hipLaunchKernelGGL(k_am_group<TRAJ_MODE_BF16X3>, dim3((unsigned)blocks), dim3(WAVE * GROUP_WAVES), 0, stream, a,
+                       L);
+  else
+    hipLaunchKernelGGL(k_am_group<TRAJ_MODE_FP32>, dim3((unsigned)blocks), dim3(WAVE * GROUP_WAVES), 0, stream, a, L);
+  return hipGetLastError();
+}
+
+}  // namespace traj

@@ -38,7 +38,16 @@ constexpr int BND_MBP = BND_MBY + NC * NY;
 constexpr int BND_M0BX = BND_MBP + NC * NP;
 constexpr int BND_M0BY = BND_M0BX + NC * NX;
 constexpr int BND_SIZE = BND_M0BY + NC * NY;
-__host__ __device__ inline int tab_size(int n) { return tab_bnd(n) + BND_SIZE; }
+// Packed product tiles of the group kernel (4-float aligned, after the boundary
+// blocks): [tile w][slot s][lane l] float4 for 16-sample tiles w. Lane l = 16 q + j
+// of slot s < 3 holds the evaluation operand of basis s (P, P', P''): entries
+// [t = 16 w + j][k = 4 q .. 4 q + 3]; slot 3 + s the contraction operand of basis s:
+// entries [t = 16 w + 4 q + r][k = j], r = 0..3. Zero outside the n x NC matrix.
+constexpr int TILE_T = 16;
+constexpr int PACK_SLOTS = 6;
+__host__ __device__ inline int n_tiles(int n) { return (n + TILE_T - 1) / TILE_T; }
+__host__ __device__ inline int tab_pack(int n) { return (tab_bnd(n) + BND_SIZE + 3) & ~3; }
+__host__ __device__ inline int tab_size(int n) { return tab_pack(n) + n_tiles(n) * PACK_SLOTS * WAVE * 4; }
 
 // FP64 table per shape: the 5 KKT inverses (KMAX x KMAX each, verification),
 // then the operators of the x/y step that stay in FP64 in the solver:
@@ -115,5 +124,12 @@ hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t st
 hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
 size_t mfma_smem_bytes(int max_n, int max_m);
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
+
+// Group kernel (one wavefront per goal group, cost-sorted work list).
+// work: int32 workspace of group_work_ints(n_scenes, n_goals, G) entries.
+int64_t group_work_ints(int n_scenes, int n_goals, int G);
+hipError_t group_blocks_per_cu(int mode, int* blocks);
+hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
+                              int32_t* work, hipStream_t stream);
 
 }  // namespace traj

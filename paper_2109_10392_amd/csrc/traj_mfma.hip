@@ -25,151 +25,30 @@
 //   BF16x3: v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo (bf16 each):
 //           hi*hi + lo*hi + hi*lo in two instructions (K = 32 holds hi and lo of
 //           16 K values), FP32 accumulation, for every contraction and apply.
-#include "traj_device.h"
+#include "traj_mma.h"
 
 namespace traj {
 namespace {
 
 using namespace dev;
+using namespace mma;
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-constexpr int TILE = 16;  // time samples per wave
-constexpr int GCOLS = 16;  // goals per MFMA
-
-__device__ __forceinline__ f4 mma32(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4 mmabf(bf8 a, bf8 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ __bf16 bf_hi(float x) { return (__bf16)x; }
-__device__ __forceinline__ __bf16 bf_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
-
-// B operand of a split product from the lane's 4 values: K slots 8q + e hold
-// hi(v[e]) for e < 4 and lo(v[e - 4]) for e >= 4.
-__device__ __forceinline__ bf8 split_b(const f4& v) {
-  bf8 b;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    b[e] = bf_hi(v[e]);
-    b[e + 4] = bf_lo(v[e]);
-  }
-  return b;
-}
-// A operands of a split product from 4 values a[e] (K slots 8q + e and 8q + e + 4):
-// first instruction hi(a) against (hi, lo) of B, second lo(a) against hi of B.
-__device__ __forceinline__ void split_a(const float (&a)[4], bf8& first, bf8& second) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    first[e] = bf_hi(a[e]);
-    first[e + 4] = bf_hi(a[e]);
-    second[e] = bf_lo(a[e]);
-    second[e + 4] = (__bf16)0.f;
-  }
-}
-
+// Constant operands of one wave: its time tile of the three basis matrices (for
+// evaluation and for the transposed contraction) and the apply operators.
 template <int MODE>
-struct Ops;
-
-// FP32: per matrix 4 K-steps of one float each.
-template <>
-struct Ops<TRAJ_MODE_FP32> {
-  float ev[3][4];   // evaluation: P, P', P'' [t = 16w + j][4q + kk]
-  float ct[3][4];   // contraction: P, P', P'' [16w + 4q + r][j]
-  double mgx[4], mx[4], mgy[4], my[4];  // x/y applies (rows permuted for the f64 output layout)
-  float mp[4];      // heading apply
+struct Ops {
+  Operand<MODE> ev[3];  // P, P', P'' [t = 16w + j][4q + kk]
+  Operand<MODE> ct[3];  // P, P', P'' [16w + 4q + r][j]
+  ApplyOps<MODE> ap;
 };
 
-// BF16x3: per matrix two split instructions.
-template <>
-struct Ops<TRAJ_MODE_BF16X3> {
-  bf8 ev[3][2];
-  bf8 ct[3][2];
-  bf8 mgx[2], mx[2], mgy[2], my[2], mp[2];
-};
-
-// evaluation of matrix `mi` at the lane's 4 samples for coefficients c (rows 4q + r)
 template <int MODE>
-__device__ __forceinline__ f4 eval(const Ops<MODE>& O, int mi, const f4& c, const bf8& cb) {
-  f4 acc = {0.f, 0.f, 0.f, 0.f};
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.ev[mi][kk], c[kk], acc);
-  } else {
-    acc = mmabf(O.ev[mi][0], cb, acc);
-    acc = mmabf(O.ev[mi][1], cb, acc);
-  }
-  return acc;
+__device__ __forceinline__ f4 evalO(const Ops<MODE>& O, int mi, const f4& c, const bf8& cb) {
+  return eval<MODE>(O.ev[mi], c, cb);
 }
-
-// accumulate the contraction of matrix `mi` against per-sample values s (lane's 4 samples)
 template <int MODE>
-__device__ __forceinline__ f4 contract(const Ops<MODE>& O, int mi, const f4& s, f4 acc) {
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc = mma32(O.ct[mi][r], s[r], acc);
-  } else {
-    const bf8 sb = split_b(s);
-    acc = mmabf(O.ct[mi][0], sb, acc);
-    acc = mmabf(O.ct[mi][1], sb, acc);
-  }
-  return acc;
-}
-
-// c0 + MG c + M r for one axis
-template <int MODE>
-__device__ __forceinline__ f4 apply_xy(const Ops<MODE>& O, int axis, const d4& c0d, const f4& c0f, const f4& c,
-                                       const f4& r) {
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-    const double* mg = axis == 0 ? O.mgx : O.mgy;
-    const double* m = axis == 0 ? O.mx : O.my;
-    d4 acc = c0d;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma64(mg[kk], (double)c[kk], acc);
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma64(m[kk], (double)r[kk], acc);
-    f4 out;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = (float)acc[k];
-    return out;
-  } else {
-    const bf8* mg = axis == 0 ? O.mgx : O.mgy;
-    const bf8* m = axis == 0 ? O.mx : O.my;
-    const bf8 cb = split_b(c), rb = split_b(r);
-    f4 acc = c0f;
-    acc = mmabf(mg[0], cb, acc);
-    acc = mmabf(mg[1], cb, acc);
-    acc = mmabf(m[0], rb, acc);
-    acc = mmabf(m[1], rb, acc);
-    return acc;
-  }
-}
-
-template <int MODE>
-__device__ __forceinline__ f4 apply_psi(const Ops<MODE>& O, const f4& c0p, const f4& r) {
-  f4 acc = c0p;
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.mp[kk], r[kk], acc);
-  } else {
-    const bf8 rb = split_b(r);
-    acc = mmabf(O.mp[0], rb, acc);
-    acc = mmabf(O.mp[1], rb, acc);
-  }
-  return acc;
-}
-
-__device__ __forceinline__ float4 f4to(const f4& v) { return make_float4(v[0], v[1], v[2], v[3]); }
-__device__ __forceinline__ f4 tof4(const float4& v) {
-  f4 r = {v.x, v.y, v.z, v.w};
-  return r;
+__device__ __forceinline__ f4 contractO(const Ops<MODE>& O, int mi, const f4& s, f4 acc) {
+  return contract<MODE>(O.ct[mi], s, acc);
 }
 
 // Sum two per-lane vectors over the workgroup's waves (fixed order: identical in
@@ -189,18 +68,6 @@ __device__ __forceinline__ void exchange(float4* ex, int buf, int W, int w, int 
   b = sb;
 }
 
-// sum over the 4 row groups (lanes j, j+16, j+32, j+48), result in every lane
-__device__ __forceinline__ float sum_rows(float v) {
-  const auto a = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
-                                                  false, false);
-  const unsigned a0 = a[0], a1 = a[1];
-  const float s = __builtin_bit_cast(float, a0) + __builtin_bit_cast(float, a1);
-  const auto b = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, s), __builtin_bit_cast(unsigned, s),
-                                                  false, false);
-  const unsigned b0 = b[0], b1 = b[1];
-  return __builtin_bit_cast(float, b0) + __builtin_bit_cast(float, b1);
-}
-
 struct Consts {
   int n, m, n_pad, W;
   float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2;
@@ -209,8 +76,6 @@ struct Consts {
 template <int MODE>
 __device__ void load_ops(Ops<MODE>& O, const float* __restrict__ T, const double* __restrict__ T64, int n, int w,
                          int j, int q) {
-  // row-permutation of the f64 16x16x4 output: register r of row group q is row 4r + q
-  const int prow = 4 * (j & 3) + (j >> 2);
 #pragma unroll
   for (int mi = 0; mi < 3; ++mi) {
     float ev[4], ct[4];
@@ -221,46 +86,10 @@ __device__ void load_ops(Ops<MODE>& O, const float* __restrict__ T, const double
       const int t2 = TILE * w + 4 * q + kk;
       ct[kk] = (t2 < n && j < NC) ? T[tab_basis(n, mi) + j * n + t2] : 0.f;
     }
-    if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        O.ev[mi][kk] = ev[kk];
-        O.ct[mi][kk] = ct[kk];
-      }
-    } else {
-      split_a(ev, O.ev[mi][0], O.ev[mi][1]);
-      split_a(ct, O.ct[mi][0], O.ct[mi][1]);
-    }
+    make_operand<MODE>(O.ev[mi], ev);
+    make_operand<MODE>(O.ct[mi], ct);
   }
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * q + kk;
-      const bool ok = prow < NC && k < NC;
-      O.mgx[kk] = ok ? T64[T64_MGX + prow * NC + k] : 0.0;
-      O.mx[kk] = ok ? T64[T64_MX + prow * NC + k] : 0.0;
-      O.mgy[kk] = ok ? T64[T64_MGY + prow * NC + k] : 0.0;
-      O.my[kk] = ok ? T64[T64_MY + prow * NC + k] : 0.0;
-      O.mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
-    }
-  } else {
-    float mgx[4], mx[4], mgy[4], my[4], mp[4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * q + kk;
-      const bool ok = j < NC && k < NC;
-      mgx[kk] = ok ? (float)T64[T64_MGX + j * NC + k] : 0.f;
-      mx[kk] = ok ? (float)T64[T64_MX + j * NC + k] : 0.f;
-      mgy[kk] = ok ? (float)T64[T64_MGY + j * NC + k] : 0.f;
-      my[kk] = ok ? (float)T64[T64_MY + j * NC + k] : 0.f;
-      mp[kk] = ok ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
-    }
-    split_a(mgx, O.mgx[0], O.mgx[1]);
-    split_a(mx, O.mx[0], O.mx[1]);
-    split_a(mgy, O.mgy[0], O.mgy[1]);
-    split_a(my, O.my[0], O.my[1]);
-    split_a(mp, O.mp[0], O.mp[1]);
-  }
+  load_apply_ops<MODE>(O.ap, T, T64, n, j, q);
 }
 
 // Per-sample closed forms for the lane's 4 samples and the contraction inputs.
@@ -507,23 +336,23 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   // (summed over the workgroup) and the lane's residual partials
   auto heading = [&](f4& xd, f4& yd, f4& th, f4& W_, f4& E_) {
     const bf8 cxb = split(cx), cyb = split(cy);
-    xd = eval<MODE>(O, 1, cx, cxb);
-    yd = eval<MODE>(O, 1, cy, cyb);
+    xd = evalO<MODE>(O, 1, cx, cxb);
+    yd = evalO<MODE>(O, 1, cy, cyb);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool tv = gv && (TILE * w + 4 * q + r) < n;
       th[r] = tv ? atan2f(yd[r], xd[r]) : 0.f;
     }
-    W_ = contract<MODE>(O, 0, th, zero);
-    E_ = contract<MODE>(O, 0, ep, zero);
+    W_ = contractO<MODE>(O, 0, th, zero);
+    E_ = contractO<MODE>(O, 0, ep, zero);
     exchange(ex, buf, Wl, w, lane, W_, E_);
     buf ^= 1;
   };
   auto project = [&](const f4& xd, const f4& yd, const f4& th) {
     const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
-    const f4 x = eval<MODE>(O, 0, cx, cxb), y = eval<MODE>(O, 0, cy, cyb);
-    const f4 xdd = eval<MODE>(O, 2, cx, cxb), ydd = eval<MODE>(O, 2, cy, cyb);
-    const f4 psi = eval<MODE>(O, 0, cp, cpb);
+    const f4 x = evalO<MODE>(O, 0, cx, cxb), y = evalO<MODE>(O, 0, cy, cyb);
+    const f4 xdd = evalO<MODE>(O, 2, cx, cxb), ydd = evalO<MODE>(O, 2, cy, cyb);
+    const f4 psi = evalO<MODE>(O, 0, cp, cpb);
     SampleOut so;
     samples(K, xi, box, w, lane, q, gv, x, y, xd, yd, xdd, ydd, psi, th, so);
     ep = so.ep;
@@ -531,12 +360,12 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
     racc[1] = so.r_acc;
     racc[2] = so.r_nh;
     racc[3] = so.r_psi;
-    f4 ax = contract<MODE>(O, 0, so.sox, zero);
-    ax = contract<MODE>(O, 2, so.sax, ax);
-    ax = contract<MODE>(O, 1, so.ex, ax);
-    f4 ay = contract<MODE>(O, 0, so.soy, zero);
-    ay = contract<MODE>(O, 2, so.say, ay);
-    ay = contract<MODE>(O, 1, so.ey, ay);
+    f4 ax = contractO<MODE>(O, 0, so.sox, zero);
+    ax = contractO<MODE>(O, 2, so.sax, ax);
+    ax = contractO<MODE>(O, 1, so.ex, ax);
+    f4 ay = contractO<MODE>(O, 0, so.soy, zero);
+    ay = contractO<MODE>(O, 2, so.say, ay);
+    ay = contractO<MODE>(O, 1, so.ey, ay);
     exchange(ex, buf, Wl, w, lane, ax, ay);
     buf ^= 1;
     ux = ax;
@@ -555,7 +384,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   {
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
-    if (cold) cp = apply_psi<MODE>(O, c0p, rho * W_ + lp);
+    if (cold) cp = apply_psi<MODE>(O.ap, c0p, rho * W_ + lp);
     project(xd, yd, th);
     ep = zero;  // the start has no pending heading multiplier step
   }
@@ -563,13 +392,13 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   bool stopped = false;
   for (int it = 0; it < A.iters; ++it) {
     // x/y step (eq. 12 through eq. 18)
-    cx = apply_xy<MODE>(O, 0, c0xd, c0xf, cx, rho * ux + lx);
-    cy = apply_xy<MODE>(O, 1, c0yd, c0yf, cy, rho * uy + ly);
+    cx = apply_xy<MODE>(O.ap, 0, c0xd, c0xf, cx, rho * ux + lx);
+    cy = apply_xy<MODE>(O.ap, 1, c0yd, c0yf, cy, rho * uy + ly);
     // pending heading multiplier (eq. 24) and heading step (eq. 13 through eq. 20)
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
     lp = lp + rho * E_;
-    cp = apply_psi<MODE>(O, c0p, rho * W_ + lp);
+    cp = apply_psi<MODE>(O.ap, c0p, rho * W_ + lp);
     // v, (alpha, d), (alpha_a, d_a) and u~ (eqs. 14-16, 21, 22)
     project(xd, yd, th);
     // multipliers of the x/y block (eq. 23)
@@ -590,7 +419,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
     }
   }
   if (done > 0) {
-    f4 E_ = contract<MODE>(O, 0, ep, zero), dummy = zero;
+    f4 E_ = contractO<MODE>(O, 0, ep, zero), dummy = zero;
     exchange(ex, buf, Wl, w, lane, E_, dummy);
     buf ^= 1;
     lp = lp + rho * E_;

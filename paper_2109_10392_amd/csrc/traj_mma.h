@@ -1,0 +1,275 @@
+// Matrix-core building blocks shared by the two MFMA solver kernels.
+//
+// Layout of a 16 x 16 product tile (v_mfma_*_16x16x*): lane l of a wave holds
+// column j = l % 16 and row group q = l / 16, i.e. output rows 4q + r (r = 0..3)
+// of column j. In the solver the column is a goal and the rows are either 16
+// time samples (after a basis evaluation) or the 11 coefficients padded to 16
+// (after a contraction over time or an 11 x 11 apply). The K index of every
+// product is chosen so that a lane's B operand is exactly the four values it
+// already holds; the constant A operands are permuted to match when loaded.
+//
+// Two precisions:
+//   FP32:   v_mfma_f32_16x16x4_f32 for evaluations, contractions and the heading
+//           apply; v_mfma_f64_16x16x4_f64 for the x/y applies, whose constant
+//           operators stay FP64.
+//   BF16x3: v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo (bf16 each):
+//           hi*hi + lo*hi + hi*lo in two instructions (K = 32 holds hi and lo of
+//           16 K values), FP32 accumulation, for every contraction and apply.
+#pragma once
+#include "traj_device.h"
+
+namespace traj {
+namespace mma {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int TILE = 16;   // time samples per product tile
+constexpr int GCOLS = 16;  // goals per product tile
+
+__device__ __forceinline__ f4 mma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mmabf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ __bf16 bf_hi(float x) { return (__bf16)x; }
+__device__ __forceinline__ __bf16 bf_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
+
+// B operand of a split product from the lane's 4 values: K slots 8q + e hold
+// hi(v[e]) for e < 4 and lo(v[e - 4]) for e >= 4.
+__device__ __forceinline__ bf8 split_b(const f4& v) {
+  bf8 b;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    b[e] = bf_hi(v[e]);
+    b[e + 4] = bf_lo(v[e]);
+  }
+  return b;
+}
+// A operands of a split product from 4 values a[e] (K slots 8q + e and 8q + e + 4):
+// first instruction hi(a) against (hi, lo) of B, second lo(a) against hi of B.
+__device__ __forceinline__ void split_a(const float (&a)[4], bf8& first, bf8& second) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    first[e] = bf_hi(a[e]);
+    first[e + 4] = bf_hi(a[e]);
+    second[e] = bf_lo(a[e]);
+    second[e + 4] = (__bf16)0.f;
+  }
+}
+
+// A operand of one 16 x 16 x 16 product (K = the 16 rows of the lane group):
+// four FP32 K-steps, or the two split BF16 instructions.
+template <int MODE>
+struct Operand;
+template <>
+struct Operand<TRAJ_MODE_FP32> {
+  float v[4];
+};
+template <>
+struct Operand<TRAJ_MODE_BF16X3> {
+  bf8 v[2];
+};
+
+template <int MODE>
+__device__ __forceinline__ void make_operand(Operand<MODE>& o, const float (&a)[4]) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o.v[e] = a[e];
+  } else {
+    split_a(a, o.v[0], o.v[1]);
+  }
+}
+
+// Basis evaluation at the lane's 4 rows for coefficients c (rows 4q + r of the
+// lane's column); cb is the split form of c (BF16x3 only).
+template <int MODE>
+__device__ __forceinline__ f4 eval(const Operand<MODE>& a, const f4& c, const bf8& cb) {
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma32(a.v[kk], c[kk], acc);
+  } else {
+    acc = mmabf(a.v[0], cb, acc);
+    acc = mmabf(a.v[1], cb, acc);
+  }
+  return acc;
+}
+
+// acc += (the transposed basis tile) x s, s = per-sample values at the lane's 4 rows
+template <int MODE>
+__device__ __forceinline__ f4 contract(const Operand<MODE>& a, const f4& s, f4 acc) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = mma32(a.v[r], s[r], acc);
+  } else {
+    const bf8 sb = split_b(s);
+    acc = mmabf(a.v[0], sb, acc);
+    acc = mmabf(a.v[1], sb, acc);
+  }
+  return acc;
+}
+
+// Operators of the x/y and heading applies (rows of the lane's column).
+template <int MODE>
+struct ApplyOps;
+template <>
+struct ApplyOps<TRAJ_MODE_FP32> {
+  double mgx[4], mx[4], mgy[4], my[4];  // rows permuted for the f64 output layout
+  float mp[4];
+};
+template <>
+struct ApplyOps<TRAJ_MODE_BF16X3> {
+  bf8 mgx[2], mx[2], mgy[2], my[2], mp[2];
+};
+
+template <int MODE>
+__device__ __forceinline__ void load_apply_ops(ApplyOps<MODE>& O, const float* __restrict__ T,
+                                               const double* __restrict__ T64, int n, int j, int q) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+    // row permutation of the f64 16x16x4 output: register r of row group q is row 4r + q
+    const int prow = 4 * (j & 3) + (j >> 2);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * q + kk;
+      const bool ok = prow < NC && k < NC;
+      O.mgx[kk] = ok ? T64[T64_MGX + prow * NC + k] : 0.0;
+      O.mx[kk] = ok ? T64[T64_MX + prow * NC + k] : 0.0;
+      O.mgy[kk] = ok ? T64[T64_MGY + prow * NC + k] : 0.0;
+      O.my[kk] = ok ? T64[T64_MY + prow * NC + k] : 0.0;
+      O.mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
+    }
+  } else {
+    float mgx[4], mx[4], mgy[4], my[4], mp[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * q + kk;
+      const bool ok = j < NC && k < NC;
+      mgx[kk] = ok ? (float)T64[T64_MGX + j * NC + k] : 0.f;
+      mx[kk] = ok ? (float)T64[T64_MX + j * NC + k] : 0.f;
+      mgy[kk] = ok ? (float)T64[T64_MGY + j * NC + k] : 0.f;
+      my[kk] = ok ? (float)T64[T64_MY + j * NC + k] : 0.f;
+      mp[kk] = ok ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
+    }
+    split_a(mgx, O.mgx[0], O.mgx[1]);
+    split_a(mx, O.mx[0], O.mx[1]);
+    split_a(mgy, O.mgy[0], O.mgy[1]);
+    split_a(my, O.my[0], O.my[1]);
+    split_a(mp, O.mp[0], O.mp[1]);
+  }
+}
+
+// c0 + MG c + M r for one axis
+template <int MODE>
+__device__ __forceinline__ f4 apply_xy(const ApplyOps<MODE>& O, int axis, const d4& c0d, const f4& c0f, const f4& c,
+                                       const f4& r) {
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+    const double* mg = axis == 0 ? O.mgx : O.mgy;
+    const double* m = axis == 0 ? O.mx : O.my;
+    d4 acc = c0d;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma64(mg[kk], (double)c[kk], acc);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma64(m[kk], (double)r[kk], acc);
+    f4 out;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = (float)acc[k];
+    return out;
+  } else {
+    const bf8* mg = axis == 0 ? O.mgx : O.mgy;
+    const bf8* m = axis == 0 ? O.mx : O.my;
+    const bf8 cb = split_b(c), rb = split_b(r);
+    f4 acc = c0f;
+    acc = mmabf(mg[0], cb, acc);
+    acc = mmabf(mg[1], cb, acc);
+    acc = mmabf(m[0], rb, acc);
+    acc = mmabf(m[1], rb, acc);
+    return acc;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ f4 apply_psi(const ApplyOps<MODE>& O, const f4& c0p, const f4& r) {
+  f4 acc = c0p;
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.mp[kk], r[kk], acc);
+  } else {
+    const bf8 rb = split_b(r);
+    acc = mmabf(O.mp[0], rb, acc);
+    acc = mmabf(O.mp[1], rb, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ float4 f4to(const f4& v) { return make_float4(v[0], v[1], v[2], v[3]); }
+__device__ __forceinline__ f4 tof4(const float4& v) {
+  f4 r = {v.x, v.y, v.z, v.w};
+  return r;
+}
+
+// sum over the 4 row groups (lanes j, j+16, j+32, j+48), result in every lane
+__device__ __forceinline__ float sum_rows(float v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v), __builtin_bit_cast(unsigned, v),
+                                                  false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  const float s = __builtin_bit_cast(float, a0) + __builtin_bit_cast(float, a1);
+  const auto b = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, s), __builtin_bit_cast(unsigned, s),
+                                                  false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return __builtin_bit_cast(float, b0) + __builtin_bit_cast(float, b1);
+}
+
+// Boundary values (eq. 8b) of a goal and the particular parts M_b b of its three
+// steps at the lane's coefficient rows 4q + r; with cold, also the boundary-only
+// minimum-acceleration start.
+struct Particular {
+  d4 c0xd, c0yd;
+  f4 c0xf, c0yf, c0p;
+};
+
+__device__ __forceinline__ void particular(const float* __restrict__ T, const double* __restrict__ T64, int n,
+                                           const float* e, const float* gl, int q, Particular& P, bool cold, f4& cx,
+                                           f4& cy) {
+  const float bx[NX] = {e[0], e[2], e[4], gl[0]};
+  const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
+  const float bp[NP] = {e[6], e[7], 0.f, 0.f};
+  const float* Bt = T + tab_bnd(n);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k = 4 * q + r;
+    P.c0xd[r] = 0.0;
+    P.c0yd[r] = 0.0;
+    P.c0xf[r] = 0.f;
+    P.c0yf[r] = 0.f;
+    P.c0p[r] = 0.f;
+    if (k < NC) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
+      for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
+      P.c0xd[r] = sx;
+      P.c0yd[r] = sy;
+      P.c0xf[r] = (float)sx;
+      P.c0yf[r] = (float)sy;
+      float sp = 0.f;
+      for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
+      P.c0p[r] = sp;
+      if (cold) {
+        float vx = 0.f, vy = 0.f;
+        for (int i = 0; i < NX; ++i) vx = fmaf(Bt[BND_M0BX + k * NX + i], bx[i], vx);
+        for (int i = 0; i < NY; ++i) vy = fmaf(Bt[BND_M0BY + k * NY + i], by[i], vy);
+        cx[r] = vx;
+        cy[r] = vy;
+      }
+    }
+  }
+}
+
+}  // namespace mma
+}  // namespace traj

@@ -207,12 +207,37 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_setup(const ShapeDesc* shapes
   }
 }
 
+// Packed product tiles of every shape (layout next to tab_pack), from the FP32
+// basis that k_setup wrote.
+__global__ void k_pack(const ShapeDesc* __restrict__ shapes, float* __restrict__ tables) {
+  const ShapeDesc sd = shapes[blockIdx.x];
+  float* T = tables + sd.table_off;
+  const int n = sd.n;
+  float4* out = reinterpret_cast<float4*>(T + tab_pack(n));
+  const int total = n_tiles(n) * PACK_SLOTS * WAVE;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int l = e % WAVE, s = (e / WAVE) % PACK_SLOTS, w = e / (WAVE * PACK_SLOTS);
+    const int j = l & 15, q = l >> 4, mi = s % 3;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = s < 3 ? TILE_T * w + j : TILE_T * w + 4 * q + r;
+      const int k = s < 3 ? 4 * q + r : j;
+      v[r] = (t < n && k < NC) ? T[tab_basis(n, mi) + k * n + t] : 0.f;
+    }
+    out[e] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverConst& k, float* d_tables,
                         double* d_tables64, int max_n, hipStream_t stream) {
   const size_t smem = sizeof(double) * (3 * (size_t)max_n * NC + 3 * NC * NC + KMAX * 2 * KMAX + KMAX) + 16;
   hipLaunchKernelGGL(k_setup, dim3(n_shapes), dim3(SETUP_THREADS), smem, stream, d_shapes, k, d_tables, d_tables64);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack, dim3(n_shapes), dim3(256), 0, stream, d_shapes, d_tables);
   return hipGetLastError();
 }
 

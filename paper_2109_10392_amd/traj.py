@@ -24,8 +24,10 @@ TRAJ_PREC_BF16X3 = 0x10
 TRAJ_KERNEL_AUTO = 0x0
 TRAJ_KERNEL_WAVE = 0x100
 TRAJ_KERNEL_MFMA = 0x200
+TRAJ_KERNEL_GROUP = 0x400
 N_COEF = 11
-_KERNELS = {"auto": TRAJ_KERNEL_AUTO, "wave": TRAJ_KERNEL_WAVE, "mfma": TRAJ_KERNEL_MFMA}
+_KERNELS = {"auto": TRAJ_KERNEL_AUTO, "wave": TRAJ_KERNEL_WAVE, "mfma": TRAJ_KERNEL_MFMA,
+            "group": TRAJ_KERNEL_GROUP}
 _PRECISIONS = {"fp32": TRAJ_PREC_FP32, "bf16x3": TRAJ_PREC_BF16X3}
 
 
@@ -47,11 +49,11 @@ class BatchC(ctypes.Structure):
 
 class StateC(ctypes.Structure):
     _fields_ = [("c", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("resid", ctypes.c_void_p),
-                ("iters", ctypes.c_void_p)]
+                ("iters", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_ints", ctypes.c_int64)]
 
 
 class TileC(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("group", ctypes.c_int32)]
+    _fields_ = [("kernel", ctypes.c_int32), ("group", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class MetaC(ctypes.Structure):
@@ -60,7 +62,8 @@ class MetaC(ctypes.Structure):
 
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
-           "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile")
+           "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
+           "traj_work_ints")
 
 _lib = None
 
@@ -84,6 +87,7 @@ def lib():
     L.traj_debug_reduce.argtypes = [vp, vp, i32, vp]
     L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
+    L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "traj_last_error" else ctypes.c_int
     _lib = L
@@ -157,6 +161,7 @@ class DeviceState:
     lam: object    # [3, 11, G] float32
     resid: object  # [4, G] float32
     iters: object  # [G] int32
+    work: object = None  # int32 scratch of the group kernel (Solver.solve sizes it)
 
     @staticmethod
     def empty(n_goals, device="cuda"):
@@ -166,7 +171,9 @@ class DeviceState:
                            torch.zeros(n_goals, device=device, dtype=torch.int32))
 
     def c_struct(self) -> StateC:
-        return StateC(_ptr(self.c), _ptr(self.lam), _ptr(self.resid), _ptr(self.iters))
+        w = self.work
+        return StateC(_ptr(self.c), _ptr(self.lam), _ptr(self.resid), _ptr(self.iters), _ptr(w),
+                      0 if w is None else int(w.numel()))
 
 
 class Solver:
@@ -195,21 +202,38 @@ class Solver:
 
     def solve(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,
               from_state: bool = False, precision: str = "fp32", kernel: str = "auto", stream=None):
+        if kernel == "group" or (kernel == "auto" and self.get_tile()[0] == "group"):
+            self.ensure_work(batch, state)
         b = batch.c_struct()
         s = state.c_struct()
         flags = (TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD) | _PRECISIONS[precision] | _KERNELS[kernel]
         _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
                                       flags, _stream(stream)))
 
-    def set_tile(self, kernel: str, group: int = 16):
-        t = TileC(_KERNELS[kernel], int(group))
+    def set_tile(self, kernel: str, group: int = 16, persistent: bool = True):
+        t = TileC(_KERNELS[kernel], int(group), 1 if persistent else 0)
         _check(lib().traj_set_tile(self.handle, ctypes.byref(t)))
 
     def get_tile(self):
+        """(kernel, group, persistent) of the handle's tile."""
         t = TileC()
         _check(lib().traj_get_tile(self.handle, ctypes.byref(t)))
         inv = {v: k for k, v in _KERNELS.items()}
-        return inv[t.kernel], t.group
+        return inv[t.kernel], t.group, bool(t.persistent)
+
+    def work_ints(self, n_scenes: int, n_goals: int) -> int:
+        """int32 scratch entries a group-kernel solve of this batch size needs."""
+        out = ctypes.c_int64()
+        _check(lib().traj_work_ints(self.handle, int(n_scenes), int(n_goals), ctypes.byref(out)))
+        return out.value
+
+    def ensure_work(self, batch, state):
+        """Give `state` a group-kernel scratch buffer of sufficient size (allocated by
+        torch outside any solve; solves themselves never allocate)."""
+        import torch
+        need = self.work_ints(batch.n_scenes, batch.n_goals)
+        if state.work is None or state.work.numel() < need:
+            state.work = torch.zeros(need, dtype=torch.int32, device=state.c.device)
 
     def score(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, kind=0, w1=1.0, w2=1.0,
               y_rl=None, stream=None):

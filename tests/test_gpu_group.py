@@ -1,0 +1,220 @@
+"""Group kernel (one wavefront per goal group, cost-sorted work list): parity
+with the oracle, invariances, the persistent schedule and hipGraph replay.
+
+FP32 runs the 1e-4 gate of the other kernels. Goal groups are independent MFMA
+columns, so the group size and the schedule (list order or persistent claiming)
+must not change any bit of the result when no tolerance stop is used.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import traj_oracle as O
+from paper_2109_10392_amd import scenes as S
+from tests.test_gpu_parity import (PARAMS, TOL, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
+                                   undetermined_goals)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_10392_amd import traj
+    traj.lib()
+    return traj
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_group_fp32_small_parity(T, seed):
+    batch = S.workload_small(seed)
+    out = gpu_solve(T, batch, 100, kernel="group")
+    prob, st = oracle_scene(batch.scenes[0], 100)
+    print(f"seed {seed}:")
+    check_gate(out["c"], prob, batch.scenes[0], st, 100)
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_group_fp32_dense_sampled(T, persistent):
+    batch = S.workload_dense(0)
+    out = gpu_solve(T, batch, 100, kernel="group", persistent=persistent)
+    sample = [0, 1, 2, 3, 4, 5, 15, 16, 17, 255, 256, 511, 700, 1000, 1021, 1022, 1023]
+    prob, st = oracle_scene(batch.scenes[0], 100, goals=sample)
+    print(f"dense, sampled goals (persistent={persistent}):")
+    check_gate(out["c"][:, :, sample], prob, batch.scenes[0], st, 100, goals=sample)
+    assert np.all(np.isfinite(out["c"])) and np.all(np.isfinite(out["resid"]))
+
+
+def test_group_fp32_ragged(T):
+    batch = ragged_batch()
+    out = gpu_solve(T, batch, 40, kernel="group")
+    off = batch.goal_off()
+    for i, sc in enumerate(batch.scenes):
+        prob, st = oracle_scene(sc, 40)
+        print(f"scene {i} (n={sc.n_time}, m={sc.obs.shape[0]}, B={sc.goals.shape[0]}):")
+        check_gate(out["c"][:, :, off[i]:off[i + 1]], prob, sc, st, 40, max_undetermined=0.5)
+
+
+def test_group_size_and_schedule_do_not_change_results(T):
+    batch = S.Batch([S.make_scene(21, 37, 12, n_lanes=6), S.make_scene(22, 5, 3, n_lanes=4),
+                     S.make_scene(23, 20, 40, n_lanes=6, n_time=150, t_f=15.0),
+                     S.make_scene(24, 3, 0, n_lanes=4, n_time=50, t_f=5.0)])
+    ref = gpu_solve(T, batch, 30, kernel="group", group=16, persistent=True)
+    for group, persistent in ((16, False), (1, True), (5, False), (11, True)):
+        out = gpu_solve(T, batch, 30, kernel="group", group=group, persistent=persistent)
+        for k in ("c", "lam", "resid", "iters"):
+            assert np.array_equal(out[k], ref[k]), (group, persistent, k)
+
+
+def test_group_resume_equals_continuous_bitwise(T):
+    batch = S.workload_small(5)
+    full = gpu_solve(T, batch, 100, kernel="group")
+    part = gpu_solve(T, batch, 40, kernel="group")
+    rest = gpu_solve(T, batch, 60, init=dict(c=part["c"], lam=part["lam"]), kernel="group")
+    for k in ("c", "lam", "resid"):
+        assert np.array_equal(full[k], rest[k]), k
+
+
+def test_group_zero_iterations_is_the_cold_start(T):
+    batch = S.workload_small(3)
+    out = gpu_solve(T, batch, 0, kernel="group")
+    _, st = oracle_scene(batch.scenes[0], 0)
+    assert coef_err(out["c"], st).max() <= TOL
+    assert np.all(out["lam"] == 0)
+    assert np.allclose(out["resid"], st.resid, rtol=1e-3, atol=1e-4)
+
+
+def test_group_tolerance_stop(T):
+    batch = S.workload_small(2)
+    out = gpu_solve(T, batch, 300, tol=1e-3, kernel="group", group=1)
+    it = out["iters"]
+    assert np.all(it % 5 == 0) and np.all((it > 0) & (it <= 300))
+    stopped = it < 300
+    assert stopped.any()
+    assert np.all(out["resid"][:3, stopped].max(0) <= 1e-3)
+
+
+def test_group_unknown_shape_marks_scene_nan(T):
+    import torch
+    batch = S.Batch([S.make_scene(1, 5, 10), S.make_scene(2, 3, 10), S.make_scene(3, 18, 10)])
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 16)
+    db = T.DeviceBatch.from_batch(batch)
+    db.shape_id[1] = 7  # not set up
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, 20)
+    torch.cuda.synchronize()
+    r = st.resid.cpu().numpy()
+    assert np.all(np.isnan(r[:, 5:8])) and np.all(np.isfinite(r[:, :5])) and np.all(np.isfinite(r[:, 8:]))
+    solver.close()
+
+
+def test_group_needs_a_work_buffer_of_sufficient_size(T):
+    import ctypes
+
+    import torch
+    batch = S.workload_small(0)
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 4)
+    need = solver.work_ints(batch.n_scenes, batch.n_goals)
+    assert need == 4 + 2 * ((batch.n_goals + 3) // 4 + batch.n_scenes)
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    st.work = torch.zeros(need - 1, dtype=torch.int32, device="cuda")
+    b, s = db.c_struct(), st.c_struct()
+    rc = T.lib().traj_solve_batch(solver.handle, ctypes.byref(b), ctypes.byref(s), 5, 0.0, T.TRAJ_KERNEL_GROUP,
+                                  T._stream(None))
+    assert rc == -1 and b"work" in T.lib().traj_last_error()
+    solver.close()
+
+
+def test_group_repeated_solves_reuse_the_work_list(T):
+    """The list kernel resets the claim counter: back-to-back persistent solves agree."""
+    import torch
+    batch = ragged_batch()
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 8, True)
+    db = T.DeviceBatch.from_batch(batch)
+    outs = []
+    for _ in range(3):
+        st = T.DeviceState.empty(batch.n_goals)
+        solver.solve(db, st, 25)
+        outs.append(st.c.clone())
+    torch.cuda.synchronize()
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    solver.close()
+
+
+def test_group_hipgraph_replay_matches_eager(T):
+    """Work list + persistent solve + scoring captured once and replayed; every
+    replay (with eager work of the program in between) equals the eager result."""
+    import torch
+    batch = ragged_batch()
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 16, True)
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+
+    def step():
+        solver.solve(db, st, 30)
+        solver.score(db, st, v_ref, cost, best)
+
+    step()  # eager reference (also sizes the work buffer outside the capture)
+    torch.cuda.synchronize()
+    ref = [st.c.clone(), st.lam.clone(), st.resid.clone(), cost.clone(), best.clone()]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        st.c.fill_(7.0)
+        st.lam.fill_(-3.0)
+        cost.fill_(0.0)
+        best.fill_(-5)
+        junk = junk * 1.0001 + 1.0  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = [st.c, st.lam, st.resid, cost, best]
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), rep
+    solver.close()
+
+
+def test_bf16x3_group_precision_report(T):
+    """Split-BF16 form on the group kernel: error vs FP64 reported per scene."""
+    rows = []
+    for seed in range(10):
+        batch = S.workload_small(seed)
+        sc = batch.scenes[0]
+        out = gpu_solve(T, batch, 100, kernel="group", precision="bf16x3")
+        prob, st = oracle_scene(sc, 100)
+        und = undetermined_goals(prob, sc, st, 100)
+        err = coef_err(out["c"], st).max(0)
+        res_err = np.abs(out["resid"][:3] - st.resid[:3]).max(0)
+        assert np.all(np.isfinite(out["c"])) and np.all(np.isfinite(out["resid"]))
+        cg = out["c"].astype(np.float64)
+        v0 = float(sc.ego[2])
+        cost_g = O.meta_cost(prob, cg[0], cg[1], cg[2], 0, v_ref=v0)
+        cost_o = O.meta_cost(prob, st.c_x, st.c_y, st.c_psi, 0, v_ref=v0)
+        bg, bo = O.best_goal(cost_g), O.best_goal(cost_o)
+        near = bg == bo or (bg >= 0 and bo >= 0 and abs(cost_o[bg] - cost_o[bo]) <= 1e-3 * max(1.0, abs(cost_o[bo])))
+        rows.append(dict(seed=seed, coef_err_max=float(err[~und].max()), coef_err_median=float(np.median(err[~und])),
+                         resid_abs_err_max=float(res_err[~und].max()), best_gpu=bg, best_oracle=bo,
+                         best_match=bool(near), undetermined=np.flatnonzero(und).tolist()))
+        print(json.dumps(rows[-1]))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "bf16x3_group_precision_report.json"), "w") as f:
+        json.dump(rows, f, indent=1)
+    assert sum(r["best_match"] for r in rows) >= 9
