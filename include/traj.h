@@ -178,8 +178,9 @@ int traj_get_tile(void *handle, traj_tile *tile);
 /*
  * traj_work_ints -- entries of the int32 device scratch (traj_state.work) that a
  * group-kernel solve of a batch with n_scenes scenes and n_goals goals needs with
- * the handle's current group size: 4 + 2 (ceil(n_goals / group) + n_scenes). The
- * wave and MFMA kernels do not use the scratch. Host-only.
+ * the handle's current group size: 4 + 2 (ceil(n_goals / group) + n_scenes) +
+ * n_goals (claim counter, the cost-sorted list of goal groups, the goal order of
+ * every scene). The wave and MFMA kernels do not use the scratch. Host-only.
  * Errors: TRAJ_E_INVAL (NULL handle or out, negative sizes).
  */
 int traj_work_ints(void *handle, int n_scenes, int n_goals, int64_t *out);

@@ -79,12 +79,14 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--write", action="store_true", help="store the winner in tuning.json")
+    ap.add_argument("--kernels", default="wave,mfma,group", help="comma-separated kernels to sweep")
     args = ap.parse_args()
+    kernels = set(args.kernels.split(","))
     batch = S.workload_dense(0) if args.workload == "dense" else S.workload_uneven(0)
     solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
-    sweep = tune(solver, db, st, args.iters, args.precision)
+    sweep = tune(solver, db, st, args.iters, args.precision, [c for c in CANDIDATES if c[0] in kernels])
     for ms, k, g, p in sweep:
         print(f"{args.workload}/{args.precision} {k:5s} group {g:2d} persistent {int(p)}: {ms:8.3f} ms", flush=True)
     if args.write:

@@ -65,31 +65,48 @@ __device__ __forceinline__ float wave_min(float v) {
 
 __device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
 
-// sin and cos: Taylor series about 0 truncated after x^15 / x^16 for |x| <= pi/2
-// (truncation error below 1e-11, i.e. FP32 rounding dominates); larger angles
-// take the library routine.
+// sin and cos of |r| <= pi/2: Taylor series about 0 truncated after r^15 / r^16
+// (truncation error below 1e-11, so FP32 rounding dominates).
+__device__ __forceinline__ void sincos_taylor(float x, float* sn, float* cs) {
+  const float x2 = x * x;
+  float ps = -7.6471637e-13f;                 // -1/15!
+  ps = fmaf(ps, x2, 1.6059044e-10f);          //  1/13!
+  ps = fmaf(ps, x2, -2.5052108e-08f);         // -1/11!
+  ps = fmaf(ps, x2, 2.7557319e-06f);          //  1/9!
+  ps = fmaf(ps, x2, -1.9841270e-04f);         // -1/7!
+  ps = fmaf(ps, x2, 8.3333333e-03f);          //  1/5!
+  ps = fmaf(ps, x2, -1.6666667e-01f);         // -1/3!
+  *sn = fmaf(ps * x2, x, x);
+  float pc = 4.7794773e-14f;                  //  1/16!
+  pc = fmaf(pc, x2, -1.1470746e-11f);         // -1/14!
+  pc = fmaf(pc, x2, 2.0876757e-09f);          //  1/12!
+  pc = fmaf(pc, x2, -2.7557319e-07f);         // -1/10!
+  pc = fmaf(pc, x2, 2.4801587e-05f);          //  1/8!
+  pc = fmaf(pc, x2, -1.3888889e-03f);         // -1/6!
+  pc = fmaf(pc, x2, 4.1666667e-02f);          //  1/4!
+  pc = fmaf(pc, x2, -0.5f);                   // -1/2!
+  *cs = fmaf(pc, x2, 1.0f);
+}
+
+// sin and cos of a heading angle. |x| <= pi/2 (every heading the method keeps):
+// the Taylor kernel directly. Larger angles: reduction by multiples of pi/2 with
+// a three-part split of pi/2 (Cody and Waite, with fused multiply-adds; relative
+// error of the reduced argument below 1e-7 for |x| < 1e3, growing slowly beyond)
+// and the quadrant's sign/swap. Non-finite input gives NaN.
 __device__ __forceinline__ void sincos_heading(float x, float* sn, float* cs) {
   if (fabsf(x) <= 1.5707964f) {
-    const float x2 = x * x;
-    float ps = -7.6471637e-13f;                 // -1/15!
-    ps = fmaf(ps, x2, 1.6059044e-10f);          //  1/13!
-    ps = fmaf(ps, x2, -2.5052108e-08f);         // -1/11!
-    ps = fmaf(ps, x2, 2.7557319e-06f);          //  1/9!
-    ps = fmaf(ps, x2, -1.9841270e-04f);         // -1/7!
-    ps = fmaf(ps, x2, 8.3333333e-03f);          //  1/5!
-    ps = fmaf(ps, x2, -1.6666667e-01f);         // -1/3!
-    *sn = fmaf(ps * x2, x, x);
-    float pc = 4.7794773e-14f;                  //  1/16!
-    pc = fmaf(pc, x2, -1.1470746e-11f);         // -1/14!
-    pc = fmaf(pc, x2, 2.0876757e-09f);          //  1/12!
-    pc = fmaf(pc, x2, -2.7557319e-07f);         // -1/10!
-    pc = fmaf(pc, x2, 2.4801587e-05f);          //  1/8!
-    pc = fmaf(pc, x2, -1.3888889e-03f);         // -1/6!
-    pc = fmaf(pc, x2, 4.1666667e-02f);          //  1/4!
-    pc = fmaf(pc, x2, -0.5f);                   // -1/2!
-    *cs = fmaf(pc, x2, 1.0f);
+    sincos_taylor(x, sn, cs);
   } else {
-    sincosf(x, sn, cs);
+    constexpr float C1 = 1.570796371e+00f, C2 = -4.371138829e-08f, C3 = -1.715124510e-15f;  // pi/2
+    const float k = rintf(x * 6.366197467e-01f);                                              // x / (pi/2)
+    float r = fmaf(-k, C1, x);
+    r = fmaf(-k, C2, r);
+    r = fmaf(-k, C3, r);
+    float s, c;
+    sincos_taylor(r, &s, &c);
+    const int quad = (int)fminf(fmaxf(k, -16777216.f), 16777216.f) & 3;
+    *sn = quad == 0 ? s : (quad == 1 ? c : (quad == 2 ? -s : -c));
+    *cs = quad == 0 ? c : (quad == 1 ? -s : (quad == 2 ? -c : s));
   }
 }
 

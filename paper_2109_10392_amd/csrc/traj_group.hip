@@ -16,6 +16,12 @@
 // contracted from per-sample residuals). A tile's basis operands are read from
 // the packed per-shape table: one coalesced float4 per lane and matrix.
 //
+// Goal order. Within a scene the goals are ranked by final position (lateral,
+// then longitudinal) and groups take 16 consecutive goals of that order, so the
+// trajectories of a group stay close together and the box of a tile's samples,
+// against which the obstacles are culled, stays small (on the dense highway
+// scene about a quarter of the obstacles the index order leaves per tile).
+//
 // Uneven batches. The goal groups of a batch are listed by a one-workgroup list
 // kernel in decreasing order of cost (16-sample tiles x (32 + obstacles)). The
 // solver grid either takes them in list order, one per wavefront, or runs
@@ -31,12 +37,15 @@ using namespace dev;
 using namespace mma;
 
 constexpr int GROUP_WAVES = 4;      // independent wavefronts per workgroup
+constexpr int MAX_TILES = (MAX_TIME + TILE - 1) / TILE;
 constexpr int LIST_THREADS = 1024;  // list kernel: one workgroup
+constexpr int ORDER_THREADS = 1024; // goal-order kernel: one workgroup per scene
 constexpr int COST_BUCKETS = 2048;  // cost keys n_tiles * (32 + m) <= 12 * 96
 
 struct GroupArgs {
   int32_t* header;   // [0] claim counter, [1] groups listed
-  int2* items;        // (scene, first goal) of each group, decreasing cost
+  int2* items;        // (scene, first position in the scene's goal order) per group, decreasing cost
+  int32_t* perm;      // [n_goals]: goal index at each position of its scene's order
   int capacity;       // entries of items
   int G;              // goals per group, 1..16
   int persistent;
@@ -109,40 +118,109 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   }
 }
 
+// Total order on floats (NaN included) as unsigned keys.
+__device__ __forceinline__ unsigned sort_key(float v) {
+  const unsigned u = __builtin_bit_cast(unsigned, v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Goal order of every scene: rank of goal i = number of goals of the scene with a
+// smaller (y_f, x_f, index). Ranks are distinct, so perm is a permutation of each
+// scene's goal range. One workgroup per scene, O(goals^2 / threads).
+__global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* __restrict__ perm) {
+  __shared__ unsigned long long key[ORDER_THREADS];
+  const int s = blockIdx.x;
+  int g0, g1;
+  scene_goals(A, s, g0, g1);
+  for (int base = g0; base < g1; base += ORDER_THREADS) {
+    const int i = base + (int)threadIdx.x;
+    unsigned long long ki = 0;
+    if (i < g1)
+      ki = ((unsigned long long)sort_key(A.goal[2 * i + 1]) << 32) | sort_key(A.goal[2 * i]);
+    int rank = 0;
+    for (int c0 = g0; c0 < g1; c0 += ORDER_THREADS) {
+      __syncthreads();
+      const int jj = c0 + (int)threadIdx.x;
+      key[threadIdx.x] =
+          jj < g1 ? (((unsigned long long)sort_key(A.goal[2 * jj + 1]) << 32) | sort_key(A.goal[2 * jj])) : 0ull;
+      __syncthreads();
+      const int cnt = min(ORDER_THREADS, g1 - c0);
+      for (int t = 0; t < cnt; ++t) {
+        const unsigned long long kj = key[t];
+        rank += (kj < ki) || (kj == ki && c0 + t < i);
+      }
+    }
+    if (i < g1) perm[g0 + rank] = i;
+  }
+}
+
 struct GConsts {
   int n, m, nt;
   float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2, dt;
 };
 
 template <int MODE>
-__device__ __forceinline__ void tile_operand(Operand<MODE>& o, const float4* __restrict__ pk, int w, int s, int lane) {
-  const float4 v = pk[(w * PACK_SLOTS + s) * WAVE + lane];
+__device__ __forceinline__ void to_operand(Operand<MODE>& o, const float4& v) {
   const float a[4] = {v.x, v.y, v.z, v.w};
   make_operand<MODE>(o, a);
 }
 
-struct TileOut {
-  f4 sox, soy, sax, say, ex, ey, ep;
-};
-
-// Per-sample closed forms at the lane's 4 samples of tile w (eqs. 21, 22, 15, 16)
-// and the residual partials. Obstacle predictions (constant velocity) are
-// evaluated where needed; only obstacles whose box over the tile's time span,
-// inflated by the scaled half-axes plus 0.1%, meets the box of the tile's
-// trajectory samples are visited: for every other pair the scaled distance
-// exceeds 1 in FP32 too, so the result is that of visiting all obstacles.
-__device__ __forceinline__ void tile_samples(const GConsts& K, const float4* __restrict__ obs, int w, int lane, int q,
-                                             bool gv, const f4& x, const f4& y, const f4& xd, const f4& yd,
-                                             const f4& xdd, const f4& ydd, const f4& psi, const f4& th, TileOut& o,
-                                             float (&racc)[4]) {
-  bool tv[4];
-  float X[4], Y[4], Tm[4];
-  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+// Validity of the lane's 4 samples of tile w and their sample times.
+__device__ __forceinline__ void tile_rows(const GConsts& K, int w, int q, bool gv, bool (&tv)[4], float (&Tm)[4]) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = TILE * w + 4 * q + r;
     tv[r] = gv && i < K.n;
     Tm[r] = (float)i * K.dt;
+  }
+}
+
+// Acceleration polar variables (eq. 16): d_a = min(a_max, h), h = |(x'', y'')|;
+// s_a = (x'', y'') (d_a / h - 1) (zero where h <= a_max, including h = 0).
+__device__ __forceinline__ void accel_forms(const GConsts& K, const bool (&tv)[4], const f4& xdd, const f4& ydd,
+                                            f4& sax, f4& say, float& racc) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
+    const float fa = (tv[r] && h2 > K.amax2) ? K.amax * rsqrtf(h2) - 1.f : 0.f;
+    sax[r] = xdd[r] * fa;
+    say[r] = ydd[r] * fa;
+    racc = fmaf(sax[r], sax[r], fmaf(say[r], say[r], racc));
+  }
+}
+
+// Velocity (eq. 21) and the non-holonomic rows: z - x' with z = v (cos psi, sin psi);
+// the heading residual theta - psi of eq. 24.
+__device__ __forceinline__ void velocity_forms(const GConsts& K, const bool (&tv)[4], const f4& xd, const f4& yd,
+                                               const f4& psi, const f4& th, f4& ex, f4& ey, f4& ep, float& r_nh,
+                                               float& r_psi) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
+    float sn, cs;
+    sincos_heading(psi[r], &sn, &cs);
+    ex[r] = tv[r] ? fmaf(v, cs, -xd[r]) : 0.f;
+    ey[r] = tv[r] ? fmaf(v, sn, -yd[r]) : 0.f;
+    ep[r] = tv[r] ? th[r] - psi[r] : 0.f;
+    r_nh = fmaf(ex[r], ex[r], fmaf(ey[r], ey[r], r_nh));
+    r_psi = fmaf(ep[r], ep[r], r_psi);
+  }
+}
+
+// Obstacle polar variables (eqs. 15, 22) at the lane's 4 samples of tile w, in
+// units scaled by (1/a, 1/b): s_o = sum_j dx_j (d_j / du_j - 1), non-zero only
+// inside an ellipse. obs: the scene's obstacles in LDS as scaled (x, y, vx, vy).
+// Only obstacles whose box over the tile's time span, inflated by the scaled
+// half-axes plus 0.1%, meets the box of the tile's trajectory samples are
+// visited: for every other pair the scaled distance exceeds 1 in FP32 too, so the
+// result is that of visiting all obstacles.
+__device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* __restrict__ obs, int w, int lane,
+                                               const bool (&tv)[4], const float (&Tm)[4], const f4& x, const f4& y,
+                                               f4& sox, f4& soy, float& r_obs) {
+  float X[4], Y[4];
+  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
     X[r] = x[r] * K.inv_a;
     Y[r] = y[r] * K.inv_b;
     if (tv[r]) {
@@ -151,37 +229,17 @@ __device__ __forceinline__ void tile_samples(const GConsts& K, const float4* __r
       lylo = fminf(lylo, Y[r]);
       lyhi = fmaxf(lyhi, Y[r]);
     }
-    // velocity (eq. 21), heading direction, z - x'
-    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
-    float sn, cs;
-    sincos_heading(psi[r], &sn, &cs);
-    const float ex = fmaf(v, cs, -xd[r]), ey = fmaf(v, sn, -yd[r]);
-    // acceleration polar variables (eq. 16): d_a = min(a_max, h), s_a = (x'', y'') (d_a / h - 1)
-    const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
-    const float fa = h2 > K.amax2 ? K.amax * rsqrtf(h2) - 1.f : 0.f;
-    const float sax = xdd[r] * fa, say = ydd[r] * fa;
-    const float ep = th[r] - psi[r];
-    o.ex[r] = tv[r] ? ex : 0.f;
-    o.ey[r] = tv[r] ? ey : 0.f;
-    o.sax[r] = tv[r] ? sax : 0.f;
-    o.say[r] = tv[r] ? say : 0.f;
-    o.ep[r] = tv[r] ? ep : 0.f;
-    if (tv[r]) {
-      racc[1] = fmaf(sax, sax, fmaf(say, say, racc[1]));
-      racc[2] = fmaf(ex, ex, fmaf(ey, ey, racc[2]));
-      racc[3] = fmaf(ep, ep, racc[3]);
-    }
   }
-  // obstacle polar variables (eqs. 15, 22) in units scaled by (1/a, 1/b):
-  // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse
   const float xlo = wave_min(lxlo), xhi = wave_max(lxhi), ylo = wave_min(lylo), yhi = wave_max(lyhi);
   bool hit = false;
   if (lane < K.m) {
+    // the scaled prediction is monotone in the sample time: its extremes over the
+    // tile are at the first and last sample (same expression as below)
     const float4 ob = obs[lane];
     const int i0 = min(TILE * w, K.n - 1), i1 = min(TILE * w + TILE - 1, K.n - 1);
     const float t0 = (float)i0 * K.dt, t1 = (float)i1 * K.dt;
-    const float xa = fmaf(ob.z, t0, ob.x) * K.inv_a, xb = fmaf(ob.z, t1, ob.x) * K.inv_a;
-    const float ya = fmaf(ob.w, t0, ob.y) * K.inv_b, yb = fmaf(ob.w, t1, ob.y) * K.inv_b;
+    const float xa = fmaf(ob.z, t0, ob.x), xb = fmaf(ob.z, t1, ob.x);
+    const float ya = fmaf(ob.w, t0, ob.y), yb = fmaf(ob.w, t1, ob.y);
     constexpr float R = 1.001f;
     hit = (xhi > fminf(xa, xb) - R) && (xlo < fmaxf(xa, xb) + R) && (yhi > fminf(ya, yb) - R) &&
           (ylo < fmaxf(ya, yb) + R);
@@ -189,28 +247,39 @@ __device__ __forceinline__ void tile_samples(const GConsts& K, const float4* __r
   unsigned long long cand = __ballot(hit);
   float Sx[4] = {0.f, 0.f, 0.f, 0.f}, Sy[4] = {0.f, 0.f, 0.f, 0.f};
   while (cand) {
-    const int jo = __builtin_ctzll(cand);
-    cand &= cand - 1;
-    const float4 ob = obs[jo];
-    float tx[4], ty[4], qq[4];
+    // up to four candidates per round, their LDS reads issued together
+    int jj[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      tx[r] = X[r] - fmaf(ob.z, Tm[r], ob.x) * K.inv_a;
-      ty[r] = Y[r] - fmaf(ob.w, Tm[r], ob.y) * K.inv_b;
-      qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
+    for (int u = 0; u < 4; ++u) {
+      jj[u] = cand ? __builtin_ctzll(cand) : -1;
+      cand &= cand - 1;
     }
-    if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
+    float4 ob[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ob[u] = obs[jj[u] < 0 ? 0 : jj[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (jj[u] < 0) break;
+      float tx[4], ty[4], qq[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (qq[r] < 1.f) {
-          if (qq[r] > 0.f) {
-            const float f = rsqrtf(qq[r]) - 1.f;
-            Sx[r] = fmaf(tx[r], f, Sx[r]);
-            Sy[r] = fmaf(ty[r], f, Sy[r]);
-            racc[0] = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, racc[0]);
-          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
-            Sx[r] += 1.f;
-            racc[0] += K.a2;
+        tx[r] = X[r] - fmaf(ob[u].z, Tm[r], ob[u].x);
+        ty[r] = Y[r] - fmaf(ob[u].w, Tm[r], ob[u].y);
+        qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
+      }
+      if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (qq[r] < 1.f) {
+            if (qq[r] > 0.f) {
+              const float f = rsqrtf(qq[r]) - 1.f;
+              Sx[r] = fmaf(tx[r], f, Sx[r]);
+              Sy[r] = fmaf(ty[r], f, Sy[r]);
+              r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, r_obs);
+            } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
+              Sx[r] += 1.f;
+              r_obs += K.a2;
+            }
           }
         }
       }
@@ -218,21 +287,22 @@ __device__ __forceinline__ void tile_samples(const GConsts& K, const float4* __r
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    o.sox[r] = K.a * Sx[r];
-    o.soy[r] = K.b * Sy[r];
+    sox[r] = K.a * Sx[r];
+    soy[r] = K.b * Sy[r];
   }
 }
 
 template <int MODE>
-__device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int lane) {
+__device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm, int G, int scene, int pos0,
+                            int lane, float4* sobs, float4* sth, double* sc0) {
   const int j = lane & 15, q = lane >> 4;
   const int NG = A.n_goals;
   int s0, s1;
   scene_goals(A, scene, s0, s1);
-  const int gcount = min(G, s1 - g0);
+  const int gcount = min(G, s1 - pos0);
   if (gcount <= 0) return;
   const bool gv = j < gcount;
-  const int g = g0 + (gv ? j : 0);
+  const int g = perm[pos0 + (gv ? j : 0)];
   const int sid = A.shape_id[scene];
   const int o0 = A.obs_off[scene];
   const int m_scene = A.obs_off[scene + 1] - o0;
@@ -269,15 +339,47 @@ __device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int la
   const float* T = A.tables + sd.table_off;
   const double* T64 = A.tables64 + sd.table64_off;
   const float4* pk = reinterpret_cast<const float4*>(T + tab_pack(n));
-  const float4* obs = reinterpret_cast<const float4*>(A.obs) + o0;
+  // the scene's obstacles into this wave's LDS slice (read back by other lanes of
+  // the same wave only; the fence keeps the compiler from reordering across it)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  if (lane < K.m) {
+    const float4 o = reinterpret_cast<const float4*>(A.obs)[o0 + lane];
+    sobs[lane] = make_float4(o.x * K.inv_a, o.y * K.inv_b, o.z * K.inv_a, o.w * K.inv_b);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const float4* obs = sobs;
 
-  ApplyOps<MODE> ap;
-  load_apply_ops<MODE>(ap, T, T64, n, j, q);
+  // The apply operators (up to 40 registers per lane) are read from the tables
+  // (cache-resident) at each use instead of being held across the sweeps: the
+  // addresses carry an offset the compiler cannot see through (an empty asm
+  // statement), so the loop-invariant loads are not hoisted out of the loop.
+  auto apply_ops = [&]() {
+    int opaque = 0;
+    asm volatile("" : "+v"(opaque));
+    ApplyOps<MODE> ap;
+    load_apply_ops<MODE>(ap, T + opaque, T64 + opaque, n, j, q);
+    return ap;
+  };
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
   f4 cx = zero, cy = zero, cp = zero, lx = zero, ly = zero, lp = zero;
   const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
   Particular P;
   particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, cold, cx, cy);
+  if constexpr (MODE == TRAJ_MODE_FP32) {
+    // the FP64 particular parts wait in LDS between applies ([axis][r][lane])
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      sc0[(0 * 4 + r) * WAVE + lane] = P.c0xd[r];
+      sc0[(1 * 4 + r) * WAVE + lane] = P.c0yd[r];
+    }
+  }
+  auto c0d = [&](int axis) {
+    d4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = sc0[(axis * 4 + r) * WAVE + lane];
+    return v;
+  };
   if (!cold) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -298,23 +400,34 @@ __device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int la
     else return bf8{};
   };
   // heading input: W = P^T theta, theta = atan2(y', x') at every sample
+  // heading input: W = P^T theta, theta = atan2(y', x') at every sample; theta is
+  // kept in this wave's LDS slice for the projection sweep that follows
   auto heading_sweep = [&]() -> f4 {
     const bf8 cxb = split(cx), cyb = split(cy);
     f4 W = zero;
+    float4 nd = pk[(0 * PACK_SLOTS + 1) * WAVE + lane], np = pk[(0 * PACK_SLOTS + 3) * WAVE + lane];
+#pragma unroll 1
     for (int w = 0; w < K.nt; ++w) {
+      const float4 vd = nd, vp = np;
+      if (w + 1 < K.nt) {  // next tile's operands in flight while this one computes
+        nd = pk[((w + 1) * PACK_SLOTS + 1) * WAVE + lane];
+        np = pk[((w + 1) * PACK_SLOTS + 3) * WAVE + lane];
+      }
       Operand<MODE> evd, ctp;
-      tile_operand<MODE>(evd, pk, w, 1, lane);
-      tile_operand<MODE>(ctp, pk, w, 3, lane);
+      to_operand<MODE>(evd, vd);
+      to_operand<MODE>(ctp, vp);
       const f4 xd = eval<MODE>(evd, cx, cxb), yd = eval<MODE>(evd, cy, cyb);
       f4 th;
 #pragma unroll
       for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2f(yd[r], xd[r]) : 0.f;
+      sth[w * WAVE + lane] = f4to(th);
       W = contract<MODE>(ctp, th, W);
     }
     return W;
   };
   // projections at (cx, cy, cp): u~ per axis, E = P^T (theta - psi) and the
-  // lane's squared residual partials (r_obs, r_acc, r_nh, r_psi)
+  // lane's squared residual partials (r_obs, r_acc, r_nh, r_psi). Each block's
+  // per-sample values are contracted as soon as they exist.
   float racc[4];
   auto projection_sweep = [&](f4& ux, f4& uy, f4& E) {
     const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
@@ -323,30 +436,61 @@ __device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int la
     E = zero;
 #pragma unroll
     for (int k = 0; k < 4; ++k) racc[k] = 0.f;
-    for (int w = 0; w < K.nt; ++w) {
-      Operand<MODE> ev0, ev1, ev2;
-      tile_operand<MODE>(ev0, pk, w, 0, lane);
-      tile_operand<MODE>(ev1, pk, w, 1, lane);
-      tile_operand<MODE>(ev2, pk, w, 2, lane);
-      const f4 x = eval<MODE>(ev0, cx, cxb), y = eval<MODE>(ev0, cy, cyb), psi = eval<MODE>(ev0, cp, cpb);
-      const f4 xd = eval<MODE>(ev1, cx, cxb), yd = eval<MODE>(ev1, cy, cyb);
-      const f4 xdd = eval<MODE>(ev2, cx, cxb), ydd = eval<MODE>(ev2, cy, cyb);
-      f4 th;
+    // operands of the current tile; each slot is refilled with the next tile's as
+    // soon as it has been used, so the loads fly while the rest of the tile computes
+    float4 op[PACK_SLOTS];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2f(yd[r], xd[r]) : 0.f;
-      TileOut o;
-      tile_samples(K, obs, w, lane, q, gv, x, y, xd, yd, xdd, ydd, psi, th, o, racc);
-      Operand<MODE> ct0, ct1, ct2;
-      tile_operand<MODE>(ct0, pk, w, 3, lane);
-      tile_operand<MODE>(ct1, pk, w, 4, lane);
-      tile_operand<MODE>(ct2, pk, w, 5, lane);
-      ux = contract<MODE>(ct0, o.sox, ux);
-      ux = contract<MODE>(ct2, o.sax, ux);
-      ux = contract<MODE>(ct1, o.ex, ux);
-      uy = contract<MODE>(ct0, o.soy, uy);
-      uy = contract<MODE>(ct2, o.say, uy);
-      uy = contract<MODE>(ct1, o.ey, uy);
-      E = contract<MODE>(ct0, o.ep, E);
+    for (int sl = 0; sl < PACK_SLOTS; ++sl) op[sl] = pk[sl * WAVE + lane];
+#pragma unroll 1
+    for (int w = 0; w < K.nt; ++w) {
+      const bool more = w + 1 < K.nt;
+      const float4* nxt = pk + (size_t)(w + 1) * PACK_SLOTS * WAVE + lane;
+      bool tv[4];
+      float Tm[4];
+      tile_rows(K, w, q, gv, tv, Tm);
+      Operand<MODE> ev, ct;
+      {  // acceleration rows
+        to_operand<MODE>(ev, op[2]);
+        to_operand<MODE>(ct, op[5]);
+        if (more) {
+          op[2] = nxt[2 * WAVE];
+          op[5] = nxt[5 * WAVE];
+        }
+        const f4 xdd = eval<MODE>(ev, cx, cxb), ydd = eval<MODE>(ev, cy, cyb);
+        f4 sax, say;
+        accel_forms(K, tv, xdd, ydd, sax, say, racc[1]);
+        ux = contract<MODE>(ct, sax, ux);
+        uy = contract<MODE>(ct, say, uy);
+      }
+      {  // velocity rows and the heading residual
+        to_operand<MODE>(ev, op[1]);
+        to_operand<MODE>(ct, op[4]);
+        if (more) {
+          op[1] = nxt[1 * WAVE];
+          op[4] = nxt[4 * WAVE];
+        }
+        const f4 xd = eval<MODE>(ev, cx, cxb), yd = eval<MODE>(ev, cy, cyb);
+        to_operand<MODE>(ev, op[0]);
+        const f4 psi = eval<MODE>(ev, cp, cpb);
+        const f4 th = tof4(sth[w * WAVE + lane]);
+        f4 ex, ey, ep;
+        velocity_forms(K, tv, xd, yd, psi, th, ex, ey, ep, racc[2], racc[3]);
+        ux = contract<MODE>(ct, ex, ux);
+        uy = contract<MODE>(ct, ey, uy);
+        to_operand<MODE>(ct, op[3]);
+        E = contract<MODE>(ct, ep, E);
+      }
+      {  // obstacle rows
+        const f4 x = eval<MODE>(ev, cx, cxb), y = eval<MODE>(ev, cy, cyb);
+        if (more) {
+          op[0] = nxt[0 * WAVE];
+          op[3] = nxt[3 * WAVE];
+        }
+        f4 sox, soy;
+        obstacle_forms(K, obs, w, lane, tv, Tm, x, y, sox, soy, racc[0]);
+        ux = contract<MODE>(ct, sox, ux);
+        uy = contract<MODE>(ct, soy, uy);
+      }
     }
   };
 
@@ -355,17 +499,26 @@ __device__ void solve_group(const SolveArgs& A, int G, int scene, int g0, int la
     // split variables of the starting point: heading QP (cold start only), v,
     // (alpha, d), (alpha_a, d_a); no multiplier is updated here
     const f4 W = heading_sweep();
-    if (cold) cp = apply_psi<MODE>(ap, P.c0p, rho * W + lp);
+    if (cold) cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
     projection_sweep(ux, uy, E);
   }
   int done = 0;
+#pragma unroll 1
   for (int it = 0; it < A.iters; ++it) {
     // x/y step (eq. 12 through eq. 18)
-    cx = apply_xy<MODE>(ap, 0, P.c0xd, P.c0xf, cx, rho * ux + lx);
-    cy = apply_xy<MODE>(ap, 1, P.c0yd, P.c0yf, cy, rho * uy + ly);
+    {
+      const ApplyOps<MODE> ap = apply_ops();
+      if constexpr (MODE == TRAJ_MODE_FP32) {
+        cx = apply_xy<MODE>(ap, 0, c0d(0), P.c0xf, cx, rho * ux + lx);
+        cy = apply_xy<MODE>(ap, 1, c0d(1), P.c0yf, cy, rho * uy + ly);
+      } else {
+        cx = apply_xy<MODE>(ap, 0, P.c0xd, P.c0xf, cx, rho * ux + lx);
+        cy = apply_xy<MODE>(ap, 1, P.c0yd, P.c0yf, cy, rho * uy + ly);
+      }
+    }
     // heading step (eq. 13 through eq. 20)
     const f4 W = heading_sweep();
-    cp = apply_psi<MODE>(ap, P.c0p, rho * W + lp);
+    cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
     // v, (alpha, d), (alpha_a, d_a), then the multipliers (eqs. 23, 24)
     projection_sweep(ux, uy, E);
     lx = lx + rho * ux;
@@ -409,24 +562,34 @@ __device__ __forceinline__ int claim(int32_t* header) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(WAVE * GROUP_WAVES) void k_am_group(SolveArgs A, GroupArgs L) {
+__global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A, GroupArgs L) {
+  __shared__ float4 sobs[GROUP_WAVES][MAX_OBS];           // each wave's current scene's obstacles (scaled)
+  __shared__ float4 sth[GROUP_WAVES][MAX_TILES * WAVE];    // each wave's theta at its lanes' samples
+  __shared__ double sc0[GROUP_WAVES][2 * 4 * WAVE];        // each wave's FP64 particular parts (x, y)
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
   const int n_items = L.header[1];
   int idx = L.persistent ? claim(L.header) : (int)blockIdx.x * GROUP_WAVES + wv;
   // every wavefront leaves once the list is exhausted: the counter only grows
   while (idx < n_items) {
     const int2 it = L.items[idx];
-    solve_group<MODE>(A, L.G, it.x, it.y, lane);
+    solve_group<MODE>(A, L.perm, L.G, it.x, it.y, lane, sobs[wv], sth[wv], sc0[wv]);
     idx = L.persistent ? claim(L.header) : n_items;
   }
 }
 
 }  // namespace
 
-int64_t group_work_ints(int n_scenes, int n_goals, int G) {
+namespace {
+// groups listed at most: sum_s ceil(goals_s / G) <= ceil(goals / G) + scenes
+int64_t group_capacity(int n_scenes, int n_goals, int G) {
   if (G < 1) G = 1;
-  // header (4) + (scene, first goal) per group; sum_s ceil(goals_s / G) <= goals / G + scenes
-  return 4 + 2 * ((int64_t)(n_goals + G - 1) / G + (int64_t)n_scenes);
+  return (int64_t)(n_goals + G - 1) / G + (int64_t)n_scenes;
+}
+}  // namespace
+
+int64_t group_work_ints(int n_scenes, int n_goals, int G) {
+  // header (4) | (scene, first position) per group | goal order [n_goals]
+  return 4 + 2 * group_capacity(n_scenes, n_goals, G) + (int64_t)n_goals;
 }
 
 hipError_t group_blocks_per_cu(int mode, int* blocks) {
@@ -439,16 +602,20 @@ hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persiste
                               int32_t* work, hipStream_t stream) {
   if (a.n_goals <= 0) return hipSuccess;
   if (G < 1 || G > GCOLS || work == nullptr) return hipErrorInvalidValue;
-  const int64_t cap64 = (group_work_ints(a.n_scenes, a.n_goals, G) - 4) / 2;
-  if (cap64 > (int64_t)1 << 30) return hipErrorInvalidValue;
+  const int64_t cap64 = group_capacity(a.n_scenes, a.n_goals, G);
+  if (cap64 > (int64_t)1 << 29) return hipErrorInvalidValue;
   GroupArgs L;
   L.header = work;
   L.items = reinterpret_cast<int2*>(work + 4);
+  L.perm = work + 4 + 2 * cap64;
   L.capacity = (int)cap64;
   L.G = G;
   L.persistent = persistent ? 1 : 0;
-  hipLaunchKernelGGL(k_list, dim3(1), dim3(LIST_THREADS), 0, stream, a, L);
+  hipLaunchKernelGGL(k_order, dim3(a.n_scenes), dim3(ORDER_THREADS), 0, stream, a, L.perm);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_list, dim3(1), dim3(LIST_THREADS), 0, stream, a, L);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   int64_t blocks = (cap64 + GROUP_WAVES - 1) / GROUP_WAVES;
   if (persistent && resident_blocks > 0 && blocks > resident_blocks) blocks = resident_blocks;
