@@ -73,6 +73,73 @@ def cpu_baseline(scene, iters, n_goals_sample):
                       f"1 BLAS thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
 
 
+def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent, one_launch_ms):
+    """The uneven batch as one hipGraph replay and as one launch per scene.
+
+    graph: the whole step (work list, persistent solve, scoring) captured once and
+    replayed; separate: the same kernels and tile, each scene solved and scored by
+    its own calls (its own one-scene batch and state), back to back on one stream.
+    """
+    import torch
+
+    def step():
+        solver.solve(db, st, args.iters, precision=args.precision)
+        solver.score(db, st, v_ref, cost, best)
+
+    step()
+    torch.cuda.synchronize()
+    ref_c = st.c.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / args.steps
+    graph_equal = bool(torch.equal(st.c, ref_c))
+
+    # one launch per scene: per-scene batches and states (goal-fastest layouts do
+    # not allow views of one scene inside the batch state)
+    parts = []
+    for sc in batch.scenes:
+        one = S.Batch([sc])
+        dbs = T.DeviceBatch.from_batch(one, shapes=batch.shapes())
+        sts = T.DeviceState.empty(one.n_goals)
+        vr = torch.tensor([float(sc.ego[2])], device="cuda")
+        parts.append((dbs, sts, vr, torch.zeros(one.n_goals, device="cuda"),
+                      torch.zeros(1, device="cuda", dtype=torch.int32)))
+
+    def separate():
+        for dbs, sts, vr, cs, bs in parts:
+            solver.solve(dbs, sts, args.iters, precision=args.precision)
+            solver.score(dbs, sts, vr, cs, bs)
+
+    separate()
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    a.record()
+    for _ in range(reps):
+        separate()
+    b.record()
+    torch.cuda.synchronize()
+    sep_ms = a.elapsed_time(b) / reps
+    off = batch.goal_off()
+    sep_equal = all(torch.equal(p[1].c, ref_c[:, :, off[i]:off[i + 1]]) for i, p in enumerate(parts))
+    return {"one_launch_ms": one_launch_ms, "graph_replay_ms": graph_ms, "separate_launches_ms": sep_ms,
+            "speedup_vs_separate": sep_ms / graph_ms, "graph_equals_eager": graph_equal,
+            "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,8 +245,11 @@ def main():
                                  if MEASURED_TRAFFIC["sources_sha256"] == solver_sources_hash() else None),
                      "kernel": "k_am (fused AM solve)", "kernel_ms": solve_avg_s * 1e3,
                      "algorithmic_flop_per_launch": flops},
-        "best_goal": int(best.item()),
+        "best_goal": int(best[0].item()),
     }
+    if args.workload == "uneven":
+        out["uneven"] = uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent,
+                                      total_ms / args.steps)
     if not args.no_cpu and args.workload == "dense":
         out["cpu_baseline"] = cpu_baseline(sc, args.iters, args.cpu_goals)
     solver.close()

@@ -39,6 +39,9 @@ extern "C" {
 /* traj_solve_batch flags */
 #define TRAJ_INIT_COLD 0x0u       /* cold start (boundary-only minimum-acceleration QP)      */
 #define TRAJ_INIT_FROM_STATE 0x1u /* start from (c, lam) in the state (resume, warm start)   */
+#define TRAJ_WARM_FALLBACK 0x2u   /* with FROM_STATE, group kernel: the first iteration also
+                                     runs from the cold start; each goal keeps whichever has
+                                     the lower max(r_obs, r_acc, r_nh) after it               */
 #define TRAJ_PREC_FP32 0x0u       /* FP32 arithmetic, x/y step operators in FP64 (default)   */
 #define TRAJ_PREC_BF16X3 0x10u    /* matrix-core kernel, every contraction and apply in split
                                      BF16 (hi + lo, three products) with FP32 accumulation   */
@@ -94,6 +97,9 @@ typedef struct {
   int32_t *work;  /* device scratch of work_ints int32 for TRAJ_KERNEL_GROUP (the work list and
                      its claim counter; contents are overwritten by every solve), else may be NULL */
   int64_t work_ints;
+  int32_t *scene_done; /* device [n_scenes] or NULL. Solve leaves every scene with a non-zero
+                          entry untouched (its goals are not iterated and nothing of theirs is
+                          written); traj_converge sets it to 1 for the converged scenes. */
 } traj_state;
 
 /* Meta-cost of Sec. III-F. */
@@ -153,6 +159,27 @@ int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, i
  */
 int traj_score(void *handle, const traj_batch *batch, const traj_state *state, const traj_metacost *mc,
                float *cost, int32_t *best, void *stream);
+
+/*
+ * traj_converge -- iterate until the stopping rule of Sec. IV (residuals of the
+ * order 1e-3 for the trajectory that is executed): chunks of `chunk` iterations,
+ * each followed by traj_score; a scene is done once its current best goal has
+ * max(r_obs, r_acc, r_nh) <= tol, and later chunks skip it. At most max_iters
+ * iterations per scene. Everything is enqueued on the stream without host
+ * synchronisation (graph-capturable); the loop length is fixed by max_iters and
+ * chunk, so finished scenes cost only the skipped launches.
+ *   flags: as traj_solve_batch for the first chunk (cold, warm, warm with
+ *          TRAJ_WARM_FALLBACK; precision; kernel); later chunks resume the state.
+ *   state: c, lam, resid and scene_done are required (scene_done is reset first
+ *          and holds 1 for converged scenes on return).
+ *   cost, best: as traj_score (the ranking after the last chunk).
+ *   scene_iters: device [n_scenes]: iterations the scene ran (a multiple of chunk,
+ *          or max_iters).
+ * Errors: TRAJ_E_INVAL (NULL arrays, tol <= 0, bad sizes), TRAJ_E_HIP.
+ */
+int traj_converge(void *handle, const traj_batch *batch, traj_state *state, const traj_metacost *mc,
+                  int max_iters, int chunk, float tol, uint32_t flags, float *cost, int32_t *best,
+                  int32_t *scene_iters, void *stream);
 
 /* Kernel tile of a handle. kernel: TRAJ_KERNEL_WAVE, TRAJ_KERNEL_MFMA or
  * TRAJ_KERNEL_GROUP; group: goals per matrix-core goal group, 1..16 (the MFMA

@@ -72,6 +72,11 @@ int check_batch(const Handle* h, const traj_batch* b) {
   return TRAJ_OK;
 }
 
+int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
+               void* stream, bool reuse_order);
+int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
+               int32_t* best, void* stream);
+
 }  // namespace
 
 extern "C" {
@@ -161,7 +166,55 @@ int traj_destroy(void* handle) {
 int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
                      void* stream) {
   g_err.clear();
+  return solve_impl((Handle*)handle, batch, state, iters, tol, flags, stream, false);
+}
+
+int traj_score(void* handle, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
+               int32_t* best, void* stream) {
+  g_err.clear();
+  return score_impl((Handle*)handle, batch, state, mc, cost, best, stream);
+}
+
+int traj_converge(void* handle, const traj_batch* batch, traj_state* state, const traj_metacost* mc, int max_iters,
+                  int chunk, float tol, uint32_t flags, float* cost, int32_t* best, int32_t* scene_iters,
+                  void* stream) {
+  g_err.clear();
   Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  int rc = check_batch(h, batch);
+  if (rc != TRAJ_OK) return rc;
+  if (state == nullptr || mc == nullptr) return fail(TRAJ_E_INVAL, "state / metacost is NULL");
+  if (max_iters < 0 || max_iters > 100000 || chunk < 1 || chunk > 100000)
+    return fail(TRAJ_E_INVAL, "max_iters must be in [0, 100000] and chunk in [1, 100000]");
+  if (!(isfinite(tol) && tol > 0.f)) return fail(TRAJ_E_INVAL, "tol must be finite and > 0");
+  if (batch->n_scenes == 0) return TRAJ_OK;
+  if (state->scene_done == nullptr || scene_iters == nullptr || best == nullptr)
+    return fail(TRAJ_E_INVAL, "state.scene_done, scene_iters and best are required");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = traj::launch_converge_reset(state->scene_done, scene_iters, batch->n_scenes, st);
+  if (e != hipSuccess) return hip_fail(e, "traj_converge");
+  const uint32_t keep = TRAJ_PREC_BF16X3 | TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA | TRAJ_KERNEL_GROUP;
+  for (int done = 0, c = 0; done < max_iters; ++c) {
+    const int it = max_iters - done < chunk ? max_iters - done : chunk;
+    // the first chunk starts as the caller asked; later chunks resume the state
+    const uint32_t f = c == 0 ? flags : ((flags & keep) | TRAJ_INIT_FROM_STATE);
+    if ((rc = solve_impl(h, batch, state, it, 0.f, f, stream, c > 0)) != TRAJ_OK) return rc;
+    if ((rc = score_impl(h, batch, state, mc, cost, best, stream)) != TRAJ_OK) return rc;
+    if (state->resid == nullptr) return fail(TRAJ_E_INVAL, "state.resid is required");
+    e = traj::launch_converge_check(batch->goal_off, state->resid, best, batch->n_scenes, batch->n_goals, it, tol,
+                                    state->scene_done, scene_iters, st);
+    if (e != hipSuccess) return hip_fail(e, "traj_converge");
+    done += it;
+  }
+  return TRAJ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
+               void* stream, bool reuse_order) {
   if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
   int rc = check_batch(h, batch);
   if (rc != TRAJ_OK) return rc;
@@ -169,8 +222,10 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   if (iters < 0 || iters > 100000) return fail(TRAJ_E_INVAL, "iters must be in [0, 100000]");
   if (!isfinite(tol)) return fail(TRAJ_E_INVAL, "tol must be finite");
   const uint32_t kernels = TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA | TRAJ_KERNEL_GROUP;
-  const uint32_t known = TRAJ_INIT_FROM_STATE | TRAJ_PREC_BF16X3 | kernels;
+  const uint32_t known = TRAJ_INIT_FROM_STATE | TRAJ_WARM_FALLBACK | TRAJ_PREC_BF16X3 | kernels;
   if ((flags & ~known) != 0) return fail(TRAJ_E_INVAL, "unknown flags 0x%x", flags);
+  if ((flags & TRAJ_WARM_FALLBACK) && !(flags & TRAJ_INIT_FROM_STATE))
+    return fail(TRAJ_E_INVAL, "TRAJ_WARM_FALLBACK needs TRAJ_INIT_FROM_STATE");
   uint32_t kernel = flags & kernels;
   if (kernel != 0 && (kernel & (kernel - 1)) != 0)
     return fail(TRAJ_E_INVAL, "TRAJ_KERNEL_WAVE, TRAJ_KERNEL_MFMA and TRAJ_KERNEL_GROUP are exclusive");
@@ -178,6 +233,8 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
     return fail(TRAJ_E_INVAL, "TRAJ_PREC_BF16X3 runs on a matrix-core kernel only");
   if (kernel == 0) kernel = (uint32_t)h->tile.kernel;
   if ((flags & TRAJ_PREC_BF16X3) && kernel == TRAJ_KERNEL_WAVE) kernel = TRAJ_KERNEL_MFMA;
+  if ((flags & TRAJ_WARM_FALLBACK) && kernel != TRAJ_KERNEL_GROUP)
+    return fail(TRAJ_E_INVAL, "TRAJ_WARM_FALLBACK runs on the group kernel only");
   if (batch->n_goals == 0) return TRAJ_OK;
   if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
   if (kernel == TRAJ_KERNEL_GROUP) {
@@ -197,6 +254,7 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   a.lam = state->lam;
   a.resid = state->resid;
   a.iters_out = state->iters;
+  a.skip = state->scene_done;
   a.shapes = h->d_shapes;
   a.tables = h->d_tables;
   a.tables64 = h->d_tables64;
@@ -211,7 +269,7 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   hipError_t e;
   if (kernel == TRAJ_KERNEL_GROUP) {
     e = traj::launch_solve_group(a, mode, h->tile.group, h->tile.persistent != 0, h->resident_blocks[mode],
-                                 state->work, (hipStream_t)stream);
+                                 state->work, reuse_order, (hipStream_t)stream);
   } else if (kernel == TRAJ_KERNEL_MFMA) {
     e = traj::launch_solve_mfma(a, mode, h->tile.group, h->max_n, h->max_m, (hipStream_t)stream);
   } else {
@@ -221,10 +279,8 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
   return TRAJ_OK;
 }
 
-int traj_score(void* handle, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
+int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
                int32_t* best, void* stream) {
-  g_err.clear();
-  Handle* h = (Handle*)handle;
   if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
   int rc = check_batch(h, batch);
   if (rc != TRAJ_OK) return rc;
@@ -257,6 +313,10 @@ int traj_score(void* handle, const traj_batch* batch, const traj_state* state, c
   if (e != hipSuccess) return hip_fail(e, "traj_score launch");
   return TRAJ_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int traj_set_tile(void* handle, const traj_tile* tile) {
   g_err.clear();

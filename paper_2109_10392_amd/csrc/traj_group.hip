@@ -76,7 +76,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
     int g0, g1;
     scene_goals(A, s, g0, g1);
-    const int cnt = (g1 - g0 + L.G - 1) / L.G;
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (g1 - g0 + L.G - 1) / L.G;
     if (cnt > 0) atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
   }
   __syncthreads();
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
     int g0, g1;
     scene_goals(A, s, g0, g1);
-    const int cnt = (g1 - g0 + L.G - 1) / L.G;
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (g1 - g0 + L.G - 1) / L.G;
     if (cnt <= 0) continue;
     int pos = atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
     for (int i = 0; i < cnt && pos < L.capacity; ++i, ++pos)
@@ -124,33 +124,44 @@ __device__ __forceinline__ unsigned sort_key(float v) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Goal order of every scene: rank of goal i = number of goals of the scene with a
-// smaller (y_f, x_f, index). Ranks are distinct, so perm is a permutation of each
-// scene's goal range. One workgroup per scene, O(goals^2 / threads).
+// Goal order of every scene: goals sorted by (y_f, x_f, index), in segments of
+// ORDER_THREADS consecutive goals (a scene with more goals is ordered segment by
+// segment). One workgroup per scene, bitonic sort of (key, index) pairs in LDS.
+// Any permutation of a scene's goal range gives the same results; the order only
+// makes the goals of a group close together.
 __global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* __restrict__ perm) {
   __shared__ unsigned long long key[ORDER_THREADS];
+  __shared__ int idx[ORDER_THREADS];
   const int s = blockIdx.x;
+  const int t = threadIdx.x;
   int g0, g1;
   scene_goals(A, s, g0, g1);
-  for (int base = g0; base < g1; base += ORDER_THREADS) {
-    const int i = base + (int)threadIdx.x;
-    unsigned long long ki = 0;
-    if (i < g1)
-      ki = ((unsigned long long)sort_key(A.goal[2 * i + 1]) << 32) | sort_key(A.goal[2 * i]);
-    int rank = 0;
-    for (int c0 = g0; c0 < g1; c0 += ORDER_THREADS) {
-      __syncthreads();
-      const int jj = c0 + (int)threadIdx.x;
-      key[threadIdx.x] =
-          jj < g1 ? (((unsigned long long)sort_key(A.goal[2 * jj + 1]) << 32) | sort_key(A.goal[2 * jj])) : 0ull;
-      __syncthreads();
-      const int cnt = min(ORDER_THREADS, g1 - c0);
-      for (int t = 0; t < cnt; ++t) {
-        const unsigned long long kj = key[t];
-        rank += (kj < ki) || (kj == ki && c0 + t < i);
+  for (int seg = g0; seg < g1; seg += ORDER_THREADS) {
+    const int cnt = min(ORDER_THREADS, g1 - seg);
+    const int i = seg + t;
+    key[t] = t < cnt ? (((unsigned long long)sort_key(A.goal[2 * i + 1]) << 32) | sort_key(A.goal[2 * i]))
+                     : ~0ull;
+    idx[t] = t;
+    __syncthreads();
+    for (int k = 2; k <= ORDER_THREADS; k <<= 1) {
+      for (int jx = k >> 1; jx > 0; jx >>= 1) {
+        const int l = t ^ jx;
+        if (l > t) {
+          const unsigned long long ka = key[t], kb = key[l];
+          const int ia = idx[t], ib = idx[l];
+          const bool a_gt = ka > kb || (ka == kb && ia > ib);
+          if (a_gt == ((t & k) == 0)) {  // out of order for this half's direction
+            key[t] = kb;
+            key[l] = ka;
+            idx[t] = ib;
+            idx[l] = ia;
+          }
+        }
+        __syncthreads();
       }
     }
-    if (i < g1) perm[g0 + rank] = i;
+    if (t < cnt) perm[seg + t] = seg + idx[t];
+    __syncthreads();
   }
 }
 
@@ -495,16 +506,14 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   };
 
   f4 ux, uy, E;
-  {
-    // split variables of the starting point: heading QP (cold start only), v,
-    // (alpha, d), (alpha_a, d_a); no multiplier is updated here
+  // split variables of a starting point: heading QP (cold start only), v, (alpha,
+  // d), (alpha_a, d_a); no multiplier is updated here
+  auto start = [&](bool cold_start) {
     const f4 W = heading_sweep();
-    if (cold) cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
+    if (cold_start) cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
     projection_sweep(ux, uy, E);
-  }
-  int done = 0;
-#pragma unroll 1
-  for (int it = 0; it < A.iters; ++it) {
+  };
+  auto iteration = [&]() {
     // x/y step (eq. 12 through eq. 18)
     {
       const ApplyOps<MODE> ap = apply_ops();
@@ -524,17 +533,13 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     lx = lx + rho * ux;
     ly = ly + rho * uy;
     lp = lp + rho * E;
-    done = it + 1;
-    if (A.tol > 0.f && done % 5 == 0) {
-      // every goal of the group at or below tol (the group advances together)
-      const float worst = sqrtf(fmaxf(fmaxf(sum_rows(racc[0]), sum_rows(racc[1])), sum_rows(racc[2])));
-      if (__ballot(gv && !(worst <= A.tol)) == 0ull) break;
-    }
-  }
-  float rr[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) rr[k] = sum_rows(racc[k]);
-  if (gv) {
+  };
+  // max(r_obs, r_acc, r_nh) of the lane's goal at the last projection sweep
+  auto worst_resid = [&]() {
+    return sqrtf(fmaxf(fmaxf(sum_rows(racc[0]), sum_rows(racc[1])), sum_rows(racc[2])));
+  };
+  auto store_state = [&]() {
+    if (!gv) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = 4 * q + r;
@@ -547,6 +552,60 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
         A.lam[(2 * NC + k) * NG + g] = lp[r];
       }
     }
+  };
+  auto load_state = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * q + r;
+      if (k < NC) {
+        cx[r] = A.c[(0 * NC + k) * NG + g];
+        cy[r] = A.c[(1 * NC + k) * NG + g];
+        cp[r] = A.c[(2 * NC + k) * NG + g];
+        lx[r] = A.lam[(0 * NC + k) * NG + g];
+        ly[r] = A.lam[(1 * NC + k) * NG + g];
+        lp[r] = A.lam[(2 * NC + k) * NG + g];
+      }
+    }
+  };
+
+  start(cold);
+  int done = 0;
+  if (!cold && (A.flags & TRAJ_WARM_FALLBACK) != 0 && A.iters > 0) {
+    // Cold start as fallback: one iteration from the given state and one from the
+    // cold start; each goal keeps the one with the lower max(r_obs, r_acc, r_nh)
+    // (a NaN residual loses). The warm result waits in the state arrays meanwhile.
+    iteration();
+    const float r_warm = worst_resid();
+    store_state();
+    lx = zero;
+    ly = zero;
+    lp = zero;
+    cp = zero;
+    particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, true, cx, cy);
+    start(true);
+    iteration();
+    const float r_cold = worst_resid();
+    const bool warm = r_warm <= r_cold;
+    if (warm && gv) load_state();
+    // the next x/y step needs u~ (and the residuals) at the kept state: one more
+    // projection sweep there reproduces them exactly (its E is not applied again)
+    if (__ballot(warm && gv) != 0ull) projection_sweep(ux, uy, E);
+    done = 1;
+  }
+#pragma unroll 1
+  for (int it = done; it < A.iters; ++it) {
+    iteration();
+    done = it + 1;
+    if (A.tol > 0.f && done % 5 == 0) {
+      // every goal of the group at or below tol (the group advances together)
+      if (__ballot(gv && !(worst_resid() <= A.tol)) == 0ull) break;
+    }
+  }
+  float rr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rr[k] = sum_rows(racc[k]);
+  store_state();
+  if (gv) {
     if (q == 0) {
       if (A.resid != nullptr)
         for (int k = 0; k < 4; ++k) A.resid[k * NG + g] = sqrtf(rr[k]);
@@ -599,7 +658,7 @@ hipError_t group_blocks_per_cu(int mode, int* blocks) {
 }
 
 hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
-                              int32_t* work, hipStream_t stream) {
+                              int32_t* work, bool reuse_order, hipStream_t stream) {
   if (a.n_goals <= 0) return hipSuccess;
   if (G < 1 || G > GCOLS || work == nullptr) return hipErrorInvalidValue;
   const int64_t cap64 = group_capacity(a.n_scenes, a.n_goals, G);
@@ -611,9 +670,12 @@ hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persiste
   L.capacity = (int)cap64;
   L.G = G;
   L.persistent = persistent ? 1 : 0;
-  hipLaunchKernelGGL(k_order, dim3(a.n_scenes), dim3(ORDER_THREADS), 0, stream, a, L.perm);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!reuse_order) {
+    hipLaunchKernelGGL(k_order, dim3(a.n_scenes), dim3(ORDER_THREADS), 0, stream, a, L.perm);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_list, dim3(1), dim3(LIST_THREADS), 0, stream, a, L);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -88,6 +88,7 @@ struct SolveArgs {
   float* lam;
   float* resid;
   int32_t* iters_out;
+  const int32_t* skip;  // [n_scenes] or NULL: scenes with a non-zero entry are left untouched
   const ShapeDesc* shapes;
   const float* tables;
   const double* tables64;
@@ -130,6 +131,13 @@ hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
 int64_t group_work_ints(int n_scenes, int n_goals, int G);
 hipError_t group_blocks_per_cu(int mode, int* blocks);
 hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
-                              int32_t* work, hipStream_t stream);
+                              int32_t* work, bool reuse_order, hipStream_t stream);
+// Convergence bookkeeping (traj_converge): zero the per-scene flags and counters;
+// after a chunk of `iters` iterations and scoring, add the chunk to every active
+// scene and mark it done when its best goal meets max(r_obs, r_acc, r_nh) <= tol.
+hipError_t launch_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes, hipStream_t stream);
+hipError_t launch_converge_check(const int32_t* goal_off, const float* resid, const int32_t* best, int n_scenes,
+                                 int n_goals, int iters, float tol, int32_t* done, int32_t* scene_iters,
+                                 hipStream_t stream);
 
 }  // namespace traj

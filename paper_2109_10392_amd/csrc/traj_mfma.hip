@@ -196,6 +196,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   locate(A.goal_off, A.n_scenes, G, sh, scan);
   const int scene = sh[0];
   if (scene < 0) return;
+  if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
   const int g0 = sh[1];
   const int gcount = min(min(G, (int)A.goal_off[scene + 1] - g0), A.n_goals - g0);
   const int sid = A.shape_id[scene];

@@ -124,7 +124,48 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
   }
 }
 
+__global__ void k_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_scenes) {
+    done[s] = 0;
+    scene_iters[s] = 0;
+  }
+}
+
+// Stopping rule of the chunked solve: a scene is converged when the residual
+// max(r_obs, r_acc, r_nh) of its current best goal is at or below tol (checked
+// after every chunk; a scene whose goals are all filtered keeps iterating).
+__global__ void k_converge_check(const int32_t* __restrict__ goal_off, const float* __restrict__ resid,
+                                 const int32_t* __restrict__ best, int n_scenes, int n_goals, int iters, float tol,
+                                 int32_t* __restrict__ done, int32_t* __restrict__ scene_iters) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_scenes || done[s] != 0) return;
+  scene_iters[s] += iters;
+  const int b = best[s];
+  if (b < 0) return;
+  const int g = goal_off[s] + b;
+  if (g < 0 || g >= n_goals) return;
+  const float worst = fmaxf(fmaxf(resid[0 * n_goals + g], resid[1 * n_goals + g]), resid[2 * n_goals + g]);
+  if (worst <= tol) done[s] = 1;
+}
+
 }  // namespace
+
+hipError_t launch_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes, hipStream_t stream) {
+  if (n_scenes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_converge_reset, dim3((n_scenes + 255) / 256), dim3(256), 0, stream, done, scene_iters,
+                     n_scenes);
+  return hipGetLastError();
+}
+
+hipError_t launch_converge_check(const int32_t* goal_off, const float* resid, const int32_t* best, int n_scenes,
+                                 int n_goals, int iters, float tol, int32_t* done, int32_t* scene_iters,
+                                 hipStream_t stream) {
+  if (n_scenes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_converge_check, dim3((n_scenes + 255) / 256), dim3(256), 0, stream, goal_off, resid, best,
+                     n_scenes, n_goals, iters, tol, done, scene_iters);
+  return hipGetLastError();
+}
 
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream) {
   (void)max_n;

@@ -417,6 +417,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   locate(A.goal_off, A.n_scenes, GOALS_PER_WG, sh, scan);
   const int scene = sh[0];
   if (scene < 0) return;
+  if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
   const int g0 = sh[1];
   const int g1 = min(min(g0 + GOALS_PER_WG, (int)A.goal_off[scene + 1]), A.n_goals);
   const int sid = A.shape_id[scene];

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libtraj.so")
 TRAJ_OK = 0
 TRAJ_INIT_COLD = 0x0
 TRAJ_INIT_FROM_STATE = 0x1
+TRAJ_WARM_FALLBACK = 0x2
 TRAJ_PREC_FP32 = 0x0
 TRAJ_PREC_BF16X3 = 0x10
 TRAJ_KERNEL_AUTO = 0x0
@@ -49,7 +50,8 @@ class BatchC(ctypes.Structure):
 
 class StateC(ctypes.Structure):
     _fields_ = [("c", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("resid", ctypes.c_void_p),
-                ("iters", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_ints", ctypes.c_int64)]
+                ("iters", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_ints", ctypes.c_int64),
+                ("scene_done", ctypes.c_void_p)]
 
 
 class TileC(ctypes.Structure):
@@ -63,7 +65,7 @@ class MetaC(ctypes.Structure):
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
-           "traj_work_ints")
+           "traj_work_ints", "traj_converge")
 
 _lib = None
 
@@ -88,6 +90,8 @@ def lib():
     L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.traj_converge.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), ctypes.POINTER(MetaC), i32, i32,
+                                f32, ctypes.c_uint32, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "traj_last_error" else ctypes.c_int
     _lib = L
@@ -162,6 +166,7 @@ class DeviceState:
     resid: object  # [4, G] float32
     iters: object  # [G] int32
     work: object = None  # int32 scratch of the group kernel (Solver.solve sizes it)
+    scene_done: object = None  # [S] int32: scenes to leave untouched (set by converge)
 
     @staticmethod
     def empty(n_goals, device="cuda"):
@@ -173,7 +178,7 @@ class DeviceState:
     def c_struct(self) -> StateC:
         w = self.work
         return StateC(_ptr(self.c), _ptr(self.lam), _ptr(self.resid), _ptr(self.iters), _ptr(w),
-                      0 if w is None else int(w.numel()))
+                      0 if w is None else int(w.numel()), _ptr(self.scene_done))
 
 
 class Solver:
@@ -200,13 +205,35 @@ class Solver:
         except Exception:
             pass
 
+    def _flags(self, from_state, fallback, precision, kernel):
+        return ((TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD) | (TRAJ_WARM_FALLBACK if fallback else 0)
+                | _PRECISIONS[precision] | _KERNELS[kernel])
+
+    def converge(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, scene_iters, max_iters=300,
+                 chunk=5, tol=1e-3, from_state=False, fallback=False, precision="fp32", kernel="auto", kind=0,
+                 w1=1.0, w2=1.0, y_rl=None, stream=None):
+        """Chunked solve until each scene's best goal meets the residual tolerance
+        (device-side bookkeeping; state.scene_done and scene_iters hold the outcome)."""
+        import torch
+        if kernel == "group" or (kernel == "auto" and self.get_tile()[0] == "group"):
+            self.ensure_work(batch, state)
+        if state.scene_done is None or state.scene_done.numel() < batch.n_scenes:
+            state.scene_done = torch.zeros(max(batch.n_scenes, 1), dtype=torch.int32, device=state.c.device)
+        b = batch.c_struct()
+        s = state.c_struct()
+        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl))
+        _check(lib().traj_converge(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), int(max_iters),
+                                   int(chunk), float(tol), self._flags(from_state, fallback, precision, kernel),
+                                   _ptr(cost), _ptr(best), _ptr(scene_iters), _stream(stream)))
+
     def solve(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,
-              from_state: bool = False, precision: str = "fp32", kernel: str = "auto", stream=None):
+              from_state: bool = False, precision: str = "fp32", kernel: str = "auto", stream=None,
+              fallback: bool = False):
         if kernel == "group" or (kernel == "auto" and self.get_tile()[0] == "group"):
             self.ensure_work(batch, state)
         b = batch.c_struct()
         s = state.c_struct()
-        flags = (TRAJ_INIT_FROM_STATE if from_state else TRAJ_INIT_COLD) | _PRECISIONS[precision] | _KERNELS[kernel]
+        flags = self._flags(from_state, fallback, precision, kernel)
         _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
                                       flags, _stream(stream)))
 

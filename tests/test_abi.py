@@ -65,8 +65,8 @@ def test_null_handle_and_null_arguments_are_errors():
 
 
 def test_struct_layouts_match_the_header():
-    # traj_state: 5 pointers + int64; traj_tile: 3 int32; traj_batch: 2 int32 + 6 pointers
-    assert ctypes.sizeof(T.StateC) == 48
+    # traj_state: 5 pointers + int64 + pointer; traj_tile: 3 int32; traj_batch: 2 int32 + 6 pointers
+    assert ctypes.sizeof(T.StateC) == 56
     assert ctypes.sizeof(T.TileC) == 12
     assert ctypes.sizeof(T.BatchC) == 56
     assert T.StateC.work_ints.offset == 40
