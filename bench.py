@@ -140,6 +140,40 @@ def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, 
             "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent]}
 
 
+def run_warmstart(args):
+    """Learned warm start: train on solved template scenes, then time cold FP32 and
+    warm + split-BF16 solves of held-out scenes to residual 1e-3 (ms per scene)."""
+    import torch
+
+    from paper_2109_10392_amd import warmstart as W
+    torch.cuda.set_device(0)
+    prob = W.Problem()
+    train_seeds = range(1000, 1000 + args.train_scenes)
+    net, mean, std, info = W.fit(prob, train_seeds, epochs=args.epochs, lr=2e-3, log=None)
+    res = W.evaluate(prob, net, mean, std, list(range(args.test_scenes)))
+    return {
+        "metric": "ms/scene to residual 1e-3 (warm+mixed vs cold FP32)",
+        "value": res["warm"]["ms_per_scene"],
+        "unit": "ms/scene",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": res["warm"]["ms_per_scene"] * args.test_scenes,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"learned warm start: template scenes (4 lanes x 64 goal slots, 10 obstacles, T=100 "
+                               f"over 10 s), network trained on {args.train_scenes} solved scenes, "
+                               f"{args.test_scenes} held-out scenes; stop when the best goal's max(r_obs, r_acc, "
+                               f"r_nh) <= 1e-3 (checked every 5 iterations, at most 300)",
+                   "train_scenes": args.train_scenes, "test_scenes": args.test_scenes, "epochs": args.epochs},
+        "cold_fp32": res["cold"], "warm_fp32": res["warm_fp32"], "warm_mixed": res["warm"],
+        "iters_ratio": res["iters_ratio"], "ms_ratio": res["ms_ratio"], "training": info,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,13 +187,20 @@ def main():
                     help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--group", type=int, default=None, help="goals per matrix-core workgroup")
-    ap.add_argument("--workload", choices=["dense", "uneven"], default="dense")
+    ap.add_argument("--workload", choices=["dense", "uneven", "warmstart"], default="dense")
+    ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")
+    ap.add_argument("--test-scenes", type=int, default=2048, help="warmstart: held-out scenes timed")
+    ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "goals are independent, so a multi-GPU run would shard scenes with no exchange inside the loop.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "warmstart":
+        print(json.dumps(run_warmstart(args)), flush=True)
+        return
 
     import torch
 

@@ -31,6 +31,23 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace traj {
+// error reporting for the entry points defined in other translation units
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace traj
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(TRAJ_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }

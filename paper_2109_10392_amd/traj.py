@@ -63,6 +63,20 @@ class MetaC(ctypes.Structure):
                 ("w2", ctypes.c_float), ("y_rl", ctypes.c_void_p)]
 
 
+class MlpDims(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+                ("n_out", ctypes.c_int32)]
+
+
+class MlpC(ctypes.Structure):
+    _fields_ = [("dims", MlpDims), ("params", ctypes.c_void_p), ("params_bf16", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p)]
+
+
+MLP_EXPORTS = ("traj_mlp_param_count", "traj_mlp_sync_bf16", "traj_features", "traj_mlp_forward", "traj_mlp_loss",
+               "traj_mlp_backward", "traj_mlp_adam", "traj_colstats", "traj_state_rows", "traj_rows_state",
+               "traj_gemm_bf16")
+
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
            "traj_work_ints", "traj_converge")
@@ -92,7 +106,19 @@ def lib():
     L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
     L.traj_converge.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), ctypes.POINTER(MetaC), i32, i32,
                                 f32, ctypes.c_uint32, vp, vp, vp, vp]
-    for name in EXPORTS:
+    P = ctypes.POINTER
+    L.traj_mlp_param_count.argtypes = [P(MlpDims), P(ctypes.c_int64)]
+    L.traj_mlp_sync_bf16.argtypes = [P(MlpC), vp]
+    L.traj_features.argtypes = [P(BatchC), vp, vp]
+    L.traj_mlp_forward.argtypes = [P(MlpC), vp, i32, vp, vp, vp]
+    L.traj_mlp_loss.argtypes = [P(MlpDims), vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    L.traj_mlp_backward.argtypes = [P(MlpC), vp, vp, i32, vp, vp]
+    L.traj_mlp_adam.argtypes = [P(MlpC), i32, f32, f32, f32, f32, vp]
+    L.traj_colstats.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.traj_state_rows.argtypes = [P(BatchC), P(StateC), i32, vp, vp]
+    L.traj_rows_state.argtypes = [P(BatchC), P(StateC), i32, vp, vp, vp, vp]
+    L.traj_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, i32, vp, vp]
+    for name in EXPORTS + MLP_EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "traj_last_error" else ctypes.c_int
     _lib = L
     return L

@@ -12,9 +12,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "traj.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(traj_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(traj_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary_calls():
@@ -27,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     L = T.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert set(T.EXPORTS) == set(declared_functions())
+    assert set(T.EXPORTS) | set(T.MLP_EXPORTS) == set(declared_functions())
 
 
 def _params(**over):
@@ -79,3 +83,13 @@ def test_work_size_query_and_tile_need_a_handle():
     tile = T.TileC(T.TRAJ_KERNEL_GROUP, 16, 1)
     assert L.traj_set_tile(None, ctypes.byref(tile)) == -1
     assert L.traj_get_tile(None, ctypes.byref(tile)) == -1
+
+
+def test_mlp_dimensions_are_validated_on_the_host():
+    L = T.lib()
+    n = ctypes.c_int64(0)
+    assert L.traj_mlp_param_count(ctypes.byref(T.MlpDims(64, 256, 3, 16896)), ctypes.byref(n)) == 0
+    assert n.value == 4_490_496
+    for bad in (T.MlpDims(63, 256, 3, 16896), T.MlpDims(64, 256, 0, 16896), T.MlpDims(64, 256, 9, 16896)):
+        assert L.traj_mlp_param_count(ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert L.traj_gemm_bf16(0, 0, 12, 16, 16, None, None, None, 0, None, None) == -1
