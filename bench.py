@@ -73,7 +73,8 @@ def cpu_baseline(scene, iters, n_goals_sample):
                       f"1 BLAS thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
 
 
-def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent, one_launch_ms):
+def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent, one_launch_ms,
+                  waves=1):
     """The uneven batch as one hipGraph replay and as one launch per scene.
 
     graph: the whole step (work list, persistent solve, scoring) captured once and
@@ -137,7 +138,7 @@ def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, 
     sep_equal = all(torch.equal(p[1].c, ref_c[:, :, off[i]:off[i + 1]]) for i, p in enumerate(parts))
     return {"one_launch_ms": one_launch_ms, "graph_replay_ms": graph_ms, "separate_launches_ms": sep_ms,
             "speedup_vs_separate": sep_ms / graph_ms, "graph_equals_eager": graph_equal,
-            "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent]}
+            "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent, waves]}
 
 
 def run_warmstart(args):
@@ -187,6 +188,7 @@ def main():
                     help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--group", type=int, default=None, help="goals per matrix-core workgroup")
+    ap.add_argument("--waves", type=int, default=None, choices=[1, 2], help="wave kernel: wavefronts per goal")
     ap.add_argument("--workload", choices=["dense", "uneven", "warmstart"], default="dense")
     ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")
     ap.add_argument("--test-scenes", type=int, default=2048, help="warmstart: held-out scenes timed")
@@ -213,18 +215,20 @@ def main():
     n, m, B = sc.n_time, sc.obs.shape[0], batch.n_goals
     solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
     kernel = args.kernel
-    persistent = True
+    persistent, waves = True, 1
     if kernel == "auto":
         from paper_2109_10392_amd import autotune
         tile = autotune.lookup(args.workload, args.precision)
-        kernel, group, persistent = (tile if tile is not None else ("wave", 16, True))
+        kernel, group, persistent, waves = (tile if tile is not None else ("wave", 16, True, 1))
     else:
         group = 16
     if args.group is not None:
         group = args.group
+    if args.waves is not None:
+        waves = args.waves
     if args.precision == "bf16x3" and kernel == "wave":
         kernel = "mfma"
-    solver.set_tile(kernel, group, persistent)
+    solver.set_tile(kernel, group, persistent, waves)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(B)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
@@ -279,7 +283,8 @@ def main():
                    {"workload": "uneven batch: 512 scenes, goals log-uniform 16-1024, obstacles U{4..64}, "
                                 "T in {50,100,150}, 100 AM iterations (cold start) + scoring",
                     "goals": B, "scenes": batch.n_scenes})
-        | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group, "persistent": persistent},
+        | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group, "persistent": persistent,
+           "waves": waves},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
@@ -290,7 +295,7 @@ def main():
     }
     if args.workload == "uneven":
         out["uneven"] = uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent,
-                                      total_ms / args.steps)
+                                      total_ms / args.steps, waves)
     if not args.no_cpu and args.workload == "dense":
         out["cpu_baseline"] = cpu_baseline(sc, args.iters, args.cpu_goals)
     solver.close()

@@ -186,18 +186,22 @@ int traj_converge(void *handle, const traj_batch *batch, traj_state *state, cons
  * has 16 goal columns; fewer goals per group spread a small batch over more
  * compute units); persistent (group kernel): 1 = a device-filling grid whose
  * wavefronts claim goal groups from the work list until it is exhausted, 0 = one
- * wavefront per listed group. */
+ * wavefront per listed group; waves (wave kernel): wavefronts per goal, 1 or 2 (two
+ * halve each wave's time samples and add their partial sums through LDS, for
+ * batches too small to fill the device with one wave per goal). */
 typedef struct {
   int32_t kernel;
   int32_t group;
   int32_t persistent;
+  int32_t waves;
 } traj_tile;
 
 /*
  * traj_set_tile / traj_get_tile -- the tile used when traj_solve_batch is called
  * with TRAJ_KERNEL_AUTO (the default). Chosen by the autotuner for a workload;
  * the initial setting is {TRAJ_KERNEL_WAVE, 16}. Host-only, no device work.
- * Errors: TRAJ_E_INVAL (unknown kernel, group outside 1..16).
+ * Errors: TRAJ_E_INVAL (unknown kernel, group outside 1..16, persistent not 0/1,
+ * waves not 1/2).
  */
 int traj_set_tile(void *handle, const traj_tile *tile);
 int traj_get_tile(void *handle, traj_tile *tile);

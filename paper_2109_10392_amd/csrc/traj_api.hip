@@ -60,7 +60,7 @@ struct Handle {
   double* d_tables64 = nullptr;
   int max_n = 0, max_m = 0;
   size_t table_floats = 0;
-  traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16, 1};
+  traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16, 1, 1};
   int resident_blocks[2] = {0, 0};  // group kernel workgroups resident at once, per precision mode
 };
 
@@ -290,7 +290,7 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
   } else if (kernel == TRAJ_KERNEL_MFMA) {
     e = traj::launch_solve_mfma(a, mode, h->tile.group, h->max_n, h->max_m, (hipStream_t)stream);
   } else {
-    e = traj::launch_solve(a, h->max_n, h->max_m, (hipStream_t)stream);
+    e = traj::launch_solve(a, h->max_n, h->max_m, h->tile.waves, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(e, "traj_solve_batch launch");
   return TRAJ_OK;
@@ -344,6 +344,7 @@ int traj_set_tile(void* handle, const traj_tile* tile) {
     return fail(TRAJ_E_INVAL, "unknown kernel 0x%x", (unsigned)tile->kernel);
   if (tile->group < 1 || tile->group > 16) return fail(TRAJ_E_INVAL, "group must be in [1, 16]");
   if (tile->persistent != 0 && tile->persistent != 1) return fail(TRAJ_E_INVAL, "persistent must be 0 or 1");
+  if (tile->waves != 1 && tile->waves != 2) return fail(TRAJ_E_INVAL, "waves must be 1 or 2");
   h->tile = *tile;
   return TRAJ_OK;
 }

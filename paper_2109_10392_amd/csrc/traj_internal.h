@@ -121,7 +121,7 @@ struct ScoreArgs {
 // Launchers (defined next to their kernels). Return hipSuccess or the launch error.
 hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverConst& k, float* d_tables,
                         double* d_tables64, int max_n, hipStream_t stream);
-hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t stream);
+hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, int waves, hipStream_t stream);
 hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
 size_t mfma_smem_bytes(int max_n, int max_m);
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);

@@ -1,9 +1,14 @@
 // Batched alternating minimisation (Algorithm 1, Sec. III-D) on gfx950.
 //
-// Mapping: one wavefront per goal, lanes over time samples (lane l holds samples
-// l, l+64, ...: S "slots"), four goals (waves) of one scene per workgroup so the
-// scene's obstacle predictions are staged once in LDS. Each goal's iterate
-// stays in registers for all iterations; nothing goes back to HBM until the end.
+// Mapping: one goal per WPG wavefronts (1 or 2), lanes over time samples: wave w
+// of a goal holds the samples lane + 64 (WPG s + w) of its S "slots". With one
+// wave per goal a workgroup holds four goals of one scene; with two, a workgroup
+// is one goal, and the two waves add their partial contractions through LDS
+// after each reduction (in a fixed order, so both hold identical totals and take
+// identical decisions). Each goal's iterate stays in registers for all
+// iterations; nothing goes back to HBM until the end. Obstacle predictions are
+// evaluated where needed from the scene's obstacles staged in LDS, pre-scaled by
+// (1/a, 1/b).
 //
 // Per iteration, with c the coefficients of the previous x/y step:
 //   x/y step (eq. 12 via eqs. 17-18). F^T g splits into a part linear in c and
@@ -51,8 +56,19 @@ constexpr int H_E = 16;     // P^T (theta - psi) of the previous heading step ->
 
 struct Goal {
   int n, m;
-  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2;
+  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2, dt;
 };
+
+// Sum of one value per lane over the goal's two waves (fixed order), through a
+// double-buffered LDS slot; every wave of the goal gets the same total.
+__device__ __forceinline__ float pair_sum(float v, float* ex, int& buf) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = (threadIdx.x >> 6) & 1;
+  ex[(buf * 2 + wv) * WAVE + lane] = v;
+  __syncthreads();
+  const float r = ex[(buf * 2 + 0) * WAVE + lane] + ex[(buf * 2 + 1) * WAVE + lane];
+  buf ^= 1;
+  return r;
+}
 
 // Basis rows of the lane's samples (slot s holds sample lane + 64 s).
 template <int S>
@@ -96,17 +112,19 @@ __device__ __forceinline__ void heading_input(const Lane<S>& L, const float (&cx
 // rows and z = v (cos psi, sin psi): u~ = F_ax^T (g - F_ax c), the multiplier
 // increment of eq. 23 divided by rho, formed from per-sample residuals. Also the
 // squared residual components, and e_psi = theta - psi per slot for eq. 24.
-template <int S>
-__device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float2* __restrict__ xi,
+template <int S, int WPG>
+__device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float4* __restrict__ sobs,
                                             const float4* __restrict__ box,
                                             const float (&cx)[NC], const float (&cy)[NC], const float (&cp)[NC],
                                             const float (&xd)[S], const float (&yd)[S], const float (&th)[S],
                                             float (&ep)[S], float (&part)[32]) {
   const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = (threadIdx.x >> 6) % WPG;
 #pragma unroll
   for (int k = 0; k < 32; ++k) part[k] = 0.f;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
+    const int gs = WPG * s + wv;  // global slot of this wave's slot s
     const float x = dotc(L.P[s], cx), y = dotc(L.P[s], cy);
     const float xdd = dotc(L.Pdd[s], cx), ydd = dotc(L.Pdd[s], cy);
     const float psi = dotc(L.P[s], cp);
@@ -131,12 +149,11 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     const float ylo = wave_min(L.val[s] ? Y : inf), yhi = wave_max(L.val[s] ? Y : -inf);
     bool hit = false;
     if (lane < G.m) {
-      const float4 bx = box[s * MAX_OBS + lane];
+      const float4 bx = box[gs * MAX_OBS + lane];
       hit = (xhi > bx.x) && (xlo < bx.y) && (yhi > bx.z) && (ylo < bx.w);
     }
     unsigned long long cand = __ballot(hit);
-    const int t = L.val[s] ? lane + WAVE * s : 0;
-    const float2* q = xi + t;
+    const float tm = (float)(lane + WAVE * gs) * G.dt;
     float Sx = 0.f, Sy = 0.f, ro = 0.f;
     while (cand) {
       // up to four candidates per round, their LDS reads issued together
@@ -149,9 +166,9 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
       float tx[4], ty[4], qq[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float2 o = q[(jj[u] < 0 ? 0 : jj[u]) * G.n];
-        tx[u] = X - o.x;
-        ty[u] = Y - o.y;
+        const float4 o = sobs[jj[u] < 0 ? 0 : jj[u]];
+        tx[u] = X - fmaf(o.z, tm, o.x);
+        ty[u] = Y - fmaf(o.w, tm, o.y);
         qq[u] = jj[u] < 0 ? 2.f : fmaf(tx[u], tx[u], ty[u] * ty[u]);
       }
       if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
@@ -187,11 +204,15 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
   }
 }
 
-template <int S>
+template <int S, int WPG>
 __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float* __restrict__ T,
-                           const float2* __restrict__ xi, const float4* __restrict__ box,
-                           const double* __restrict__ apply64, int scene, int g) {
+                           const float4* __restrict__ sobs, const float4* __restrict__ box,
+                           const double* __restrict__ apply64, float* ex, int scene, int g) {
   const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = (threadIdx.x >> 6) % WPG;
+  int buf = 0;
+  // wave totals of a reduction (the pair's sum when a goal spans two waves)
+  auto total = [&](float v) { return WPG == 2 ? pair_sum(v, ex, buf) : v; };
   const int NG = A.n_goals;
   Goal G;
   G.n = sd.n;
@@ -207,13 +228,14 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   G.vmax = A.k.v_max;
   G.amax = A.k.a_max;
   G.amax2 = G.amax * G.amax;
+  G.dt = sd.t_f / (float)(sd.n - 1);
   const float rho = G.rho;
   const int n = G.n;
 
   Lane<S> L;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int t = lane + WAVE * s;
+    const int t = lane + WAVE * (WPG * s + wv);
     L.val[s] = t < n;
     const int tc = L.val[s] ? t : 0;
 #pragma unroll
@@ -295,7 +317,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     float xd[S], yd[S], th[S];
     heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
     if (cold) {
-      const float wE = reduce32(part);
+      const float wE = total(reduce32(part));
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
       const float rp = fmaf(rho, w, lp);
       float np = c0p;
@@ -304,8 +326,8 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
 #pragma unroll
       for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
     }
-    projections<S>(G, L, xi, box, cx, cy, cp, xd, yd, th, ep, part);
-    uxy = reduce32(part);
+    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part);
+    uxy = total(reduce32(part));
 #pragma unroll
     for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
   }
@@ -340,7 +362,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     float xd[S], yd[S], th[S];
     {
       heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
-      const float wE = reduce32(part);
+      const float wE = total(reduce32(part));
       lp = fmaf(rho, wE, lp);                 // upper lanes: lambda_psi += rho P^T (theta - psi)
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
       const float rp = fmaf(rho, w, lp);
@@ -351,8 +373,8 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
     }
     // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
-    projections<S>(G, L, xi, box, cx, cy, cp, xd, yd, th, ep, part);
-    uxy = reduce32(part);
+    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part);
+    uxy = total(reduce32(part));
     // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
     lxy = fmaf(rho, uxy, lxy);
     done = it + 1;
@@ -370,9 +392,10 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
 #pragma unroll
       for (int k = 0; k < NC; ++k) part[H_E + k] = fmaf(L.P[s][k], ep[s], part[H_E + k]);
     }
-    lp = fmaf(rho, reduce32(part), lp);
+    lp = fmaf(rho, total(reduce32(part)), lp);
   }
 
+  if (WPG == 2 && wv != 0) return;  // the first wave of the goal writes
   // ---- write back from the home lanes
   const int k = (lane & 31) >> 1;
   if ((lane & 1) == 0 && k < NC) {
@@ -407,64 +430,69 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   if (A.iters_out != nullptr && lane == 0) A.iters_out[g] = done;
 }
 
-template <int S>
+template <int S, int WPG>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
-  extern __shared__ float2 xi[];  // [m][n] obstacle predictions, scaled by (1/a, 1/b)
-  __shared__ float4 box[S * MAX_OBS];        // per slot and obstacle: x range, y range (scaled, inflated)
-  __shared__ double apply64[4 * NC * NC];    // MGx, Mx, MGy, My of the scene's shape
+  constexpr int GPW = WPG == 1 ? GOALS_PER_WG : 1;  // goals per workgroup
+  constexpr int THREADS = WAVE * WPG * GPW;
+  __shared__ float4 sobs[MAX_OBS];                  // the scene's obstacles, scaled by (1/a, 1/b)
+  __shared__ float4 box[S * WPG * MAX_OBS];         // per slot and obstacle: x range, y range (scaled, inflated)
+  __shared__ double apply64[4 * NC * NC];           // MGx, Mx, MGy, My of the scene's shape
+  __shared__ float ex[2 * 2 * WAVE];                // partial sums of a goal's two waves (double-buffered)
   __shared__ int sh[2];
   __shared__ int scan[GOALS_PER_WG];
-  locate(A.goal_off, A.n_scenes, GOALS_PER_WG, sh, scan);
+  locate(A.goal_off, A.n_scenes, GPW, sh, scan);
   const int scene = sh[0];
   if (scene < 0) return;
   if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
   const int g0 = sh[1];
-  const int g1 = min(min(g0 + GOALS_PER_WG, (int)A.goal_off[scene + 1]), A.n_goals);
+  const int g1 = min(min(g0 + GPW, (int)A.goal_off[scene + 1]), A.n_goals);
   const int sid = A.shape_id[scene];
   const int o0 = A.obs_off[scene];
   const int m_scene = A.obs_off[scene + 1] - o0;
   bool bad = sid < 0 || sid >= A.n_shapes;
   ShapeDesc sd = {};
   if (!bad) sd = A.shapes[sid];
-  bad = bad || m_scene != sd.m || sd.n > WAVE * S || sd.n < NC;
+  bad = bad || m_scene != sd.m || sd.n > WAVE * S * WPG || sd.n < NC;
   const int tid = threadIdx.x;
-  const int g = g0 + (tid >> 6);
+  const int g = g0 + (tid >> 6) / WPG;
+  const bool writer = ((tid >> 6) % WPG) == 0;
   if (bad) {
-    if (A.resid != nullptr && g < g1 && (tid & 63) < 4) A.resid[(tid & 63) * A.n_goals + g] = __builtin_nanf("");
-    if (A.iters_out != nullptr && g < g1 && (tid & 63) == 0) A.iters_out[g] = 0;
+    if (writer && A.resid != nullptr && g < g1 && (tid & 63) < 4)
+      A.resid[(tid & 63) * A.n_goals + g] = __builtin_nanf("");
+    if (writer && A.iters_out != nullptr && g < g1 && (tid & 63) == 0) A.iters_out[g] = 0;
     return;
   }
   const int n = sd.n, m = sd.m;
   const float dt = sd.t_f / (float)(n - 1);
   const float inv_a = 1.f / A.k.a, inv_b = 1.f / A.k.b;
-  for (int e = tid; e < m * n; e += SOLVE_THREADS) {
-    const int j = e / n, i = e - j * n;
+  for (int j = tid; j < m; j += THREADS) {
     const float* o = A.obs + 4 * (o0 + j);
-    const float t = (float)i * dt;
-    xi[e] = make_float2(fmaf(o[2], t, o[0]) * inv_a, fmaf(o[3], t, o[1]) * inv_b);
+    sobs[j] = make_float4(o[0] * inv_a, o[1] * inv_b, o[2] * inv_a, o[3] * inv_b);
   }
-  // Per-slot boxes: the staged prediction is monotone in the sample index, so its
-  // extremes over a slot are at the slot's first and last sample (same expression).
-  for (int e = tid; e < S * m; e += SOLVE_THREADS) {
-    const int s = e / m, j = e - s * m;
-    const int i0 = min(WAVE * s, n - 1), i1 = min(WAVE * s + WAVE - 1, n - 1);
+  // Per-slot boxes: the scaled prediction fma(v', t, p') is monotone in the sample
+  // time, so its extremes over a slot are at the slot's first and last sample
+  // (the same expression the projections evaluate).
+  for (int e = tid; e < S * WPG * m; e += THREADS) {
+    const int gs = e / m, j = e - gs * m;
+    const int i0 = min(WAVE * gs, n - 1), i1 = min(WAVE * gs + WAVE - 1, n - 1);
     const float* o = A.obs + 4 * (o0 + j);
+    const float px = o[0] * inv_a, py = o[1] * inv_b, vx = o[2] * inv_a, vy = o[3] * inv_b;
     const float t0 = (float)i0 * dt, t1 = (float)i1 * dt;
-    const float xa = fmaf(o[2], t0, o[0]) * inv_a, xb = fmaf(o[2], t1, o[0]) * inv_a;
-    const float ya = fmaf(o[3], t0, o[1]) * inv_b, yb = fmaf(o[3], t1, o[1]) * inv_b;
+    const float xa = fmaf(vx, t0, px), xb = fmaf(vx, t1, px);
+    const float ya = fmaf(vy, t0, py), yb = fmaf(vy, t1, py);
     constexpr float R = 1.001f;
-    box[s * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
+    box[gs * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
   }
   const double* T64 = A.tables64 + sd.table64_off;
-  for (int e = tid; e < NC * NC; e += SOLVE_THREADS) {
+  for (int e = tid; e < NC * NC; e += THREADS) {
     apply64[0 * NC * NC + e] = T64[T64_MGX + e];
     apply64[1 * NC * NC + e] = T64[T64_MX + e];
     apply64[2 * NC * NC + e] = T64[T64_MGY + e];
     apply64[3 * NC * NC + e] = T64[T64_MY + e];
   }
   __syncthreads();
-  if (g >= g1) return;
-  solve_goal<S>(A, sd, A.tables + sd.table_off, xi, box, apply64, scene, g);
+  if (g >= g1) return;  // only with one wave per goal (a two-wave workgroup always has its goal)
+  solve_goal<S, WPG>(A, sd, A.tables + sd.table_off, sobs, box, apply64, ex, scene, g);
 }
 
 // Lane-layout check of the two reductions: in[R][64] -> out[64].
@@ -483,12 +511,6 @@ __global__ void k_debug_reduce(const float* in, float* out, int r) {
   }
 }
 
-template <int S>
-hipError_t set_smem(size_t smem) {
-  if (smem <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_am<S>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-}
-
 }  // namespace
 
 hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream) {
@@ -496,20 +518,22 @@ hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, hipStream_t stream) {
+hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, int waves, hipStream_t stream) {
+  (void)max_m;
   if (a.n_goals <= 0) return hipSuccess;
-  const int blocks = (a.n_goals + GOALS_PER_WG - 1) / GOALS_PER_WG + a.n_scenes;
-  const size_t smem = sizeof(float2) * (size_t)max_n * (size_t)(max_m > 0 ? max_m : 1);
-  const int S = (max_n + WAVE - 1) / WAVE;
-  if (smem > 148 * 1024) return hipErrorInvalidValue;  // + static LDS (boxes, FP64 rows) <= 160 KiB
-  const hipError_t e = (S <= 1) ? set_smem<1>(smem) : (S == 2 ? set_smem<2>(smem) : set_smem<3>(smem));
-  if (e != hipSuccess) return e;
-  if (S <= 1)
-    hipLaunchKernelGGL(k_am<1>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
-  else if (S == 2)
-    hipLaunchKernelGGL(k_am<2>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
-  else
-    hipLaunchKernelGGL(k_am<3>, dim3(blocks), dim3(SOLVE_THREADS), smem, stream, a);
+  if (waves != 1 && waves != 2) return hipErrorInvalidValue;
+  const int gpw = waves == 1 ? GOALS_PER_WG : 1;
+  const int blocks = (a.n_goals + gpw - 1) / gpw + a.n_scenes;
+  const int S = (max_n + WAVE * waves - 1) / (WAVE * waves);
+  const dim3 block(WAVE * waves * gpw);
+  if (waves == 1) {
+    if (S <= 1) hipLaunchKernelGGL((k_am<1, 1>), dim3(blocks), block, 0, stream, a);
+    else if (S == 2) hipLaunchKernelGGL((k_am<2, 1>), dim3(blocks), block, 0, stream, a);
+    else hipLaunchKernelGGL((k_am<3, 1>), dim3(blocks), block, 0, stream, a);
+  } else {
+    if (S <= 1) hipLaunchKernelGGL((k_am<1, 2>), dim3(blocks), block, 0, stream, a);
+    else hipLaunchKernelGGL((k_am<2, 2>), dim3(blocks), block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ class StateC(ctypes.Structure):
 
 
 class TileC(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("group", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+    _fields_ = [("kernel", ctypes.c_int32), ("group", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("waves", ctypes.c_int32)]
 
 
 class MetaC(ctypes.Structure):
@@ -263,16 +264,16 @@ class Solver:
         _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
                                       flags, _stream(stream)))
 
-    def set_tile(self, kernel: str, group: int = 16, persistent: bool = True):
-        t = TileC(_KERNELS[kernel], int(group), 1 if persistent else 0)
+    def set_tile(self, kernel: str, group: int = 16, persistent: bool = True, waves: int = 1):
+        t = TileC(_KERNELS[kernel], int(group), 1 if persistent else 0, int(waves))
         _check(lib().traj_set_tile(self.handle, ctypes.byref(t)))
 
     def get_tile(self):
-        """(kernel, group, persistent) of the handle's tile."""
+        """(kernel, group, persistent, waves) of the handle's tile."""
         t = TileC()
         _check(lib().traj_get_tile(self.handle, ctypes.byref(t)))
         inv = {v: k for k, v in _KERNELS.items()}
-        return inv[t.kernel], t.group, bool(t.persistent)
+        return inv[t.kernel], t.group, bool(t.persistent), t.waves
 
     def work_ints(self, n_scenes: int, n_goals: int) -> int:
         """int32 scratch entries a group-kernel solve of this batch size needs."""

@@ -69,9 +69,9 @@ def test_null_handle_and_null_arguments_are_errors():
 
 
 def test_struct_layouts_match_the_header():
-    # traj_state: 5 pointers + int64 + pointer; traj_tile: 3 int32; traj_batch: 2 int32 + 6 pointers
+    # traj_state: 5 pointers + int64 + pointer; traj_tile: 4 int32; traj_batch: 2 int32 + 6 pointers
     assert ctypes.sizeof(T.StateC) == 56
-    assert ctypes.sizeof(T.TileC) == 12
+    assert ctypes.sizeof(T.TileC) == 16
     assert ctypes.sizeof(T.BatchC) == 56
     assert T.StateC.work_ints.offset == 40
 
@@ -80,7 +80,7 @@ def test_work_size_query_and_tile_need_a_handle():
     L = T.lib()
     out = ctypes.c_int64(-1)
     assert L.traj_work_ints(None, 1, 10, ctypes.byref(out)) == -1
-    tile = T.TileC(T.TRAJ_KERNEL_GROUP, 16, 1)
+    tile = T.TileC(T.TRAJ_KERNEL_GROUP, 16, 1, 1)
     assert L.traj_set_tile(None, ctypes.byref(tile)) == -1
     assert L.traj_get_tile(None, ctypes.byref(tile)) == -1
 

@@ -32,10 +32,10 @@ def T():
 
 
 def gpu_solve(T, batch, iters, init=None, tol=0.0, params=PARAMS, shapes=None, kernel="auto", precision="fp32",
-              group=16, persistent=True):
+              group=16, persistent=True, waves=1):
     import torch
     solver = T.Solver(params, shapes or batch.shapes())
-    solver.set_tile("wave" if kernel == "auto" else kernel, group, persistent)
+    solver.set_tile("wave" if kernel == "auto" else kernel, group, persistent, waves)
     db = T.DeviceBatch.from_batch(batch, shapes=shapes)
     st = T.DeviceState.empty(batch.n_goals)
     if init is not None:
