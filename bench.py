@@ -26,25 +26,40 @@ sys.path.insert(0, ROOT)
 N_COEF = 11
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 
-# HBM bytes per launch of the AM kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by the same counters over a plain 256 MiB copy (fetch x2.00, write
-# x1.00); see profiles/. Valid only for the kernel source they were taken on:
-# when the hash of the solver sources differs, traffic is reported as null.
+# HBM bytes per launch of the dominant kernel of each workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE, scaled by the same counters over a plain 256 MiB copy
+# (fetch x2.00, write x1.00); see profiles/. Valid only for the kernel sources
+# they were taken on: when the hash of those sources differs, traffic is null.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "73d6ac9049164652742a34fd147004e885341ea11d831f58d4a72c960effe472",
-    "bytes_per_launch": int((351.17 * 2.0 + 568.0) * 1024),
-    "profile": "profiles/k_am_wave_dense1024.md",
+    "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
+                          "paper_2109_10392_amd/csrc/traj_device.h"),
+              "sha256": "d0a2adf919edca022172f33c3afbbbc946804eb57c7979c5b76e8e410009046a",
+              "bytes_per_launch": int((280.28 * 2.0 + 2272.0) * 1024),
+              "profile": "profiles/k_am_wave2_dense1024.md"},
+    "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
+                           "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
+               "sha256": "30a9a560b3e01209fe1b4c57de22931237dea86004490fbf55bd8fac9671f682",
+               "bytes_per_launch": int((84581.9 * 2.0 + 278059.4) * 1024),
+               "profile": "profiles/k_am_group_uneven512.md"},
 }
-SOLVER_SOURCES = ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h")
 
 
-def solver_sources_hash():
+def sources_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for rel in SOLVER_SOURCES:
+    for rel in files:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def measured_traffic(workload, kernel, waves):
+    """Bytes per launch if the profiled kernel and sources are what runs, else None."""
+    m = MEASURED_TRAFFIC.get(workload)
+    expected = {"dense": ("wave", 2), "uneven": ("group", None)}[workload]
+    if m is None or kernel != expected[0] or (expected[1] is not None and waves != expected[1]):
+        return None
+    return m["bytes_per_launch"] if sources_hash(m["sources"]) == m["sha256"] else None
 
 
 def algorithmic_flops_per_goal_iter(n, m, N=N_COEF):
@@ -183,7 +198,9 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-goals", type=int, default=160)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="uneven: skip the graph-replay and separate-launch comparisons (profiling)")
+    ap.add_argument("--cpu-goals", type=int, default=640, help="goals of the CPU oracle sample (about 15 s)")
     ap.add_argument("--kernel", choices=["auto", "wave", "mfma", "group"], default="auto",
                     help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
@@ -287,13 +304,13 @@ def main():
            "waves": waves},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
-                                 if MEASURED_TRAFFIC["sources_sha256"] == solver_sources_hash() else None),
-                     "kernel": "k_am (fused AM solve)", "kernel_ms": solve_avg_s * 1e3,
+                     "traffic": measured_traffic(args.workload, kernel, waves),
+                     "kernel": {"wave": "k_am (wave kernel)", "mfma": "k_am_mfma", "group": "k_am_group"}[kernel],
+                     "kernel_ms": solve_avg_s * 1e3,
                      "algorithmic_flop_per_launch": flops},
         "best_goal": int(best[0].item()),
     }
-    if args.workload == "uneven":
+    if args.workload == "uneven" and not args.no_extras:
         out["uneven"] = uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent,
                                       total_ms / args.steps, waves)
     if not args.no_cpu and args.workload == "dense":
