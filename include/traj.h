@@ -242,6 +242,13 @@ int traj_debug_table_size(void *handle, int shape);
  */
 int traj_debug_reduce(const float *in, float *out, int r, void *stream);
 
+/*
+ * traj_debug_atan2 -- the solver's atan2 (heading angle theta = atan2(y', x') of
+ * eq. 13) applied element-wise, for checking it against a reference:
+ * out[i] = atan2(y[i], x[i]). Device arrays of n floats. Asynchronous.
+ */
+int traj_debug_atan2(const float *y, const float *x, float *out, int n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@
 
 namespace traj {
 hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream);
+hipError_t launch_debug_atan2(const float* y, const float* x, float* out, int n, hipStream_t stream);
 }
 
 namespace {
@@ -388,6 +389,14 @@ int traj_debug_operators(void* handle, int shape, double* out_f64, float* out_f3
                        st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "traj_debug_operators");
+  return TRAJ_OK;
+}
+
+int traj_debug_atan2(const float* y, const float* x, float* out, int n, void* stream) {
+  g_err.clear();
+  if (y == nullptr || x == nullptr || out == nullptr || n < 0) return fail(TRAJ_E_INVAL, "bad argument");
+  hipError_t e = traj::launch_debug_atan2(y, x, out, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traj_debug_atan2");
   return TRAJ_OK;
 }
 

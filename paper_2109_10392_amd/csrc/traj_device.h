@@ -110,6 +110,41 @@ __device__ __forceinline__ void sincos_heading(float x, float* sn, float* cs) {
   }
 }
 
+// atan2 of a heading direction. First octant: a = min(|x|, |y|) / max(|x|, |y|)
+// in [0, 1]; atan(a) = a p(a^2) with p a degree-9 polynomial in a^2 fitted for
+// relative error to atan(sqrt(s)) / sqrt(s) on [0, 1] (reweighted least squares
+// on Chebyshev nodes; 1.2 units in the last place at most in FP32 Horner form);
+// then pi/2 - r past the diagonal, pi - r for negative x (sign bit, so -0 counts)
+// and the sign of y. Special cases as IEEE atan2: (+-0, +0) -> +-0,
+// (+-0, -0) -> +-pi, both infinite -> +-pi/4 or +-3pi/4, NaN in -> NaN. Tiny
+// magnitudes are scaled by 2^100 (exact) before the reciprocal.
+__device__ __forceinline__ float atan2_heading(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float sc = mx < 0x1p-100f ? 0x1p+100f : 1.f;
+  mx *= sc;
+  mn *= sc;
+  float a = mn * __builtin_amdgcn_rcpf(mx);
+  a = (mn == mx) ? 1.f : a;   // equal magnitudes, both infinite included
+  a = (mn == 0.f) ? 0.f : a;  // an axis (both zero included)
+  const float s = a * a;
+  float p = -1.7538585e-03f;
+  p = fmaf(p, s, 1.0726622e-02f);
+  p = fmaf(p, s, -3.0803997e-02f);
+  p = fmaf(p, s, 5.7551499e-02f);
+  p = fmaf(p, s, -8.3772801e-02f);
+  p = fmaf(p, s, 1.0942019e-01f);
+  p = fmaf(p, s, -1.4261931e-01f);
+  p = fmaf(p, s, 1.9998266e-01f);
+  p = fmaf(p, s, -3.3333284e-01f);
+  p = fmaf(p, s, 1.0f);
+  float r = a * p;
+  r = (ay > ax) ? 1.57079637f - r : r;
+  r = __builtin_signbit(x) ? 3.14159274f - r : r;
+  r = copysignf(r, y);
+  return (x != x || y != y) ? x + y : r;
+}
+
 // Wave-wide sums of 32 per-lane values: on return lane l holds the sum of value l >> 1.
 __device__ __forceinline__ float reduce32(const float (&v)[32]) {
   const int lane = threadIdx.x & (WAVE - 1);

@@ -430,7 +430,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
       const f4 xd = eval<MODE>(evd, cx, cxb), yd = eval<MODE>(evd, cy, cyb);
       f4 th;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2f(yd[r], xd[r]) : 0.f;
+      for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2_heading(yd[r], xd[r]) : 0.f;
       sth[w * WAVE + lane] = f4to(th);
       W = contract<MODE>(ctp, th, W);
     }

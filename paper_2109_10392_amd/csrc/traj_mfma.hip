@@ -342,7 +342,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool tv = gv && (TILE * w + 4 * q + r) < n;
-      th[r] = tv ? atan2f(yd[r], xd[r]) : 0.f;
+      th[r] = tv ? atan2_heading(yd[r], xd[r]) : 0.f;
     }
     W_ = contractO<MODE>(O, 0, th, zero);
     E_ = contractO<MODE>(O, 0, ep, zero);

@@ -96,7 +96,7 @@ __device__ __forceinline__ void heading_input(const Lane<S>& L, const float (&cx
   for (int s = 0; s < S; ++s) {
     xd[s] = dotc(L.Pd[s], cx);
     yd[s] = dotc(L.Pd[s], cy);
-    th[s] = atan2f(yd[s], xd[s]);
+    th[s] = atan2_heading(yd[s], xd[s]);
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       part[H_W + k] = fmaf(L.P[s][k], th[s], part[H_W + k]);
@@ -511,7 +511,18 @@ __global__ void k_debug_reduce(const float* in, float* out, int r) {
   }
 }
 
+__global__ void k_debug_atan2(const float* y, const float* x, float* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = atan2_heading(y[i], x[i]);
+}
+
 }  // namespace
+
+hipError_t launch_debug_atan2(const float* y, const float* x, float* out, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_atan2, dim3((n + 255) / 256), dim3(256), 0, stream, y, x, out, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream) {
   hipLaunchKernelGGL(k_debug_reduce, dim3(1), dim3(WAVE), 0, stream, in, out, r);

@@ -80,7 +80,7 @@ MLP_EXPORTS = ("traj_mlp_param_count", "traj_mlp_sync_bf16", "traj_features", "t
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
-           "traj_work_ints", "traj_converge")
+           "traj_work_ints", "traj_converge", "traj_debug_atan2")
 
 _lib = None
 
@@ -102,6 +102,7 @@ def lib():
     L.traj_debug_operators.argtypes = [vp, i32, vp, vp, vp]
     L.traj_debug_table_size.argtypes = [vp, i32]
     L.traj_debug_reduce.argtypes = [vp, vp, i32, vp]
+    L.traj_debug_atan2.argtypes = [vp, vp, vp, i32, vp]
     L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -308,6 +309,10 @@ class Solver:
         _check(L.traj_debug_operators(self.handle, shape, f64.ctypes.data_as(ctypes.c_void_p),
                                       f32.ctypes.data_as(ctypes.c_void_p), _stream(None)))
         return f64.reshape(5, 17, 17), f32
+
+
+def debug_atan2(y_dev, x_dev, out_dev, stream=None):
+    _check(lib().traj_debug_atan2(_ptr(y_dev), _ptr(x_dev), _ptr(out_dev), int(y_dev.numel()), _stream(stream)))
 
 
 def debug_reduce(values_dev, out_dev, r, stream=None):

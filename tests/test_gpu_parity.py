@@ -113,6 +113,33 @@ def test_reduce_lane_layout(T):
         assert np.array_equal(out.cpu().numpy().astype(np.float64), expect)
 
 
+def test_heading_atan2_accuracy_and_special_cases(T):
+    """The solver's atan2 against FP64 arctan2: at most 3 units in the last place
+    over all octants and magnitudes, and IEEE results on the special cases."""
+    import torch
+    rng = np.random.default_rng(11)
+    ang = rng.uniform(-np.pi, np.pi, 200000)
+    mag = 10.0 ** rng.uniform(-30, 30, ang.size)
+    y = np.concatenate([mag * np.sin(ang), rng.normal(0, 1, 50000)]).astype(np.float32)
+    x = np.concatenate([mag * np.cos(ang), rng.normal(0, 1, 50000)]).astype(np.float32)
+    sp = [(0.0, 0.0), (-0.0, 0.0), (0.0, -0.0), (-0.0, -0.0), (1.0, 0.0), (-1.0, 0.0), (0.0, 1.0), (0.0, -1.0),
+          (np.inf, np.inf), (-np.inf, np.inf), (np.inf, -np.inf), (-np.inf, -np.inf), (3.0, np.inf), (3.0, -np.inf),
+          (np.inf, 2.0), (-np.inf, 2.0), (1e-40, 1e-40), (1e-40, 0.0), (np.nan, 1.0), (1.0, np.nan), (5.0, 5.0),
+          (-5.0, 5.0), (2.0, 1e-39)]
+    y = np.concatenate([y, np.array([p[0] for p in sp], np.float32)])
+    x = np.concatenate([x, np.array([p[1] for p in sp], np.float32)])
+    out = torch.empty(y.size, device="cuda")
+    T.debug_atan2(torch.from_numpy(y).cuda(), torch.from_numpy(x).cuda(), out)
+    got = out.cpu().numpy()
+    ref = np.arctan2(y.astype(np.float64), x.astype(np.float64))
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ulp = np.abs(got[fin] - ref[fin]) / np.spacing(np.abs(ref[fin]).astype(np.float32)).astype(np.float64)
+    assert ulp.max() <= 3.0, ulp.max()
+    k = y.size - len(sp)
+    assert np.array_equal(np.signbit(got[k:k + 4]), np.signbit(ref[k:k + 4]))  # signed zeros and pi
+
+
 @pytest.mark.parametrize("shape", [(100, 10.0, 10), (50, 5.0, 4), (150, 15.0, 64), (100, 10.0, 0)])
 def test_setup_inverses_match_oracle(T, shape):
     n, tf, m = shape
