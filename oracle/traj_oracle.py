@@ -354,3 +354,34 @@ def best_goal(cost):
     if not finite.any():
         return -1
     return int(np.flatnonzero(cost == np.min(cost[finite]))[0])
+
+
+# ------------------------------------------------------------ controls and post-check
+
+
+def controls(prob, obs, c_x, c_y, c_psi, wheelbase, v_floor):
+    """Controls along one trajectory and its clearance from the obstacles.
+
+    Acceleration is the rate of change of speed, v' = (x' x'' + y' y'') / v; the
+    steering angle follows the kinematic relation the paper states for
+    extracting it (Sec. III): arctan(psi' h / v), h the wheelbase, with v floored
+    at v_floor (the speed bound v_min). Clearance is the smallest scaled distance
+    sqrt((dx/a)^2 + (dy/b)^2) over all samples and obstacles (constant-velocity
+    predictions); a value below 1 is a collision with an obstacle ellipse (eq. 1e).
+    Returns (accel[n], steer[n], clearance).
+    """
+    xd, yd = prob.Pd @ c_x, prob.Pd @ c_y
+    xdd, ydd = prob.Pdd @ c_x, prob.Pdd @ c_y
+    psid = prob.Pd @ c_psi
+    v = np.hypot(xd, yd)
+    accel = np.where(v > 0, (xd * xdd + yd * ydd) / np.where(v > 0, v, 1.0), 0.0)
+    steer = np.arctan(psid * wheelbase / np.maximum(v, v_floor))
+    obs = np.asarray(obs, np.float64).reshape(-1, 4)
+    if obs.shape[0] == 0:
+        return accel, steer, np.inf
+    x, y = prob.P @ c_x, prob.P @ c_y
+    t = prob.t
+    xi_x = obs[:, 0][None, :] + obs[:, 2][None, :] * t[:, None]
+    xi_y = obs[:, 1][None, :] + obs[:, 3][None, :] * t[:, None]
+    du = np.sqrt(((x[:, None] - xi_x) / prob.a) ** 2 + ((y[:, None] - xi_y) / prob.b) ** 2)
+    return accel, steer, float(du.min())
