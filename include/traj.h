@@ -181,6 +181,22 @@ int traj_converge(void *handle, const traj_batch *batch, traj_state *state, cons
                   int max_iters, int chunk, float tol, uint32_t flags, float *cost, int32_t *best,
                   int32_t *scene_iters, void *stream);
 
+/*
+ * traj_controls -- controls along the chosen trajectory of every scene (the
+ * goal index best[s] from traj_score) and its clearance from the obstacles:
+ * acceleration v' = (x' x'' + y' y'') / v and steering atan(psi' h / max(v, v_min))
+ * (the relation the paper gives for extracting the steering input, Sec. III),
+ * h = wheelbase; clearance = smallest sqrt((dx/a)^2 + (dy/b)^2) over samples and
+ * obstacles with the constant-velocity predictions (< 1: the trajectory enters
+ * an obstacle ellipse of eq. 1e).
+ *   accel, steer: device [n_scenes][stride], samples 0 .. n_time - 1 of the scene;
+ *   stride >= the longest n_time of the handle. clearance: device [n_scenes]
+ *   (+inf without obstacles; NaN where best < 0 or the shape is unknown).
+ * Errors: TRAJ_E_INVAL, TRAJ_E_HIP.
+ */
+int traj_controls(void *handle, const traj_batch *batch, const traj_state *state, const int32_t *best,
+                  float wheelbase, int stride, float *accel, float *steer, float *clearance, void *stream);
+
 /* Kernel tile of a handle. kernel: TRAJ_KERNEL_WAVE, TRAJ_KERNEL_MFMA or
  * TRAJ_KERNEL_GROUP; group: goals per matrix-core goal group, 1..16 (the MFMA
  * has 16 goal columns; fewer goals per group spread a small batch over more

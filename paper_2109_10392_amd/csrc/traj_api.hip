@@ -336,6 +336,44 @@ int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, cons
 
 extern "C" {
 
+int traj_controls(void* handle, const traj_batch* batch, const traj_state* state, const int32_t* best,
+                  float wheelbase, int stride, float* accel, float* steer, float* clearance, void* stream) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  int rc = check_batch(h, batch);
+  if (rc != TRAJ_OK) return rc;
+  if (state == nullptr || state->c == nullptr || best == nullptr || accel == nullptr || steer == nullptr ||
+      clearance == nullptr)
+    return fail(TRAJ_E_INVAL, "traj_controls: NULL argument");
+  if (!(isfinite(wheelbase) && wheelbase > 0.f)) return fail(TRAJ_E_INVAL, "wheelbase must be finite and > 0");
+  if (stride < h->max_n) return fail(TRAJ_E_INVAL, "stride must be at least the longest horizon (%d)", h->max_n);
+  if (batch->n_scenes == 0) return TRAJ_OK;
+  traj::ControlArgs a;
+  a.goal_off = batch->goal_off;
+  a.obs_off = batch->obs_off;
+  a.shape_id = batch->shape_id;
+  a.obs = batch->obs;
+  a.c = state->c;
+  a.best = best;
+  a.shapes = h->d_shapes;
+  a.tables = h->d_tables;
+  a.n_shapes = (int)h->shapes.size();
+  a.n_scenes = batch->n_scenes;
+  a.n_goals = batch->n_goals;
+  a.stride = stride;
+  a.wheelbase = wheelbase;
+  a.v_floor = h->p.v_min;
+  a.a = h->p.a;
+  a.b = h->p.b;
+  a.accel = accel;
+  a.steer = steer;
+  a.clearance = clearance;
+  hipError_t e = traj::launch_controls(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "traj_controls launch");
+  return TRAJ_OK;
+}
+
 int traj_set_tile(void* handle, const traj_tile* tile) {
   g_err.clear();
   Handle* h = (Handle*)handle;

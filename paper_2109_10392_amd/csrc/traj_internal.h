@@ -118,6 +118,25 @@ struct ScoreArgs {
   int32_t* best;
 };
 
+struct ControlArgs {
+  const int32_t* goal_off;
+  const int32_t* obs_off;
+  const int32_t* shape_id;
+  const float* obs;
+  const float* c;
+  const int32_t* best;
+  const ShapeDesc* shapes;
+  const float* tables;
+  int n_shapes;
+  int n_scenes;
+  int n_goals;
+  int stride;
+  float wheelbase, v_floor, a, b;
+  float* accel;
+  float* steer;
+  float* clearance;
+};
+
 // Launchers (defined next to their kernels). Return hipSuccess or the launch error.
 hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverConst& k, float* d_tables,
                         double* d_tables64, int max_n, hipStream_t stream);
@@ -125,6 +144,7 @@ hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, int waves, hip
 hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
 size_t mfma_smem_bytes(int max_n, int max_m);
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
+hipError_t launch_controls(const ControlArgs& a, hipStream_t stream);
 
 // Group kernel (one wavefront per goal group, cost-sorted work list).
 // work: int32 workspace of group_work_ints(n_scenes, n_goals, G) entries.

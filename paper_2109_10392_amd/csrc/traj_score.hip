@@ -124,6 +124,68 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
   }
 }
 
+// Controls of the chosen trajectory of every scene and its clearance from the
+// obstacles: one wavefront per scene, lanes over time samples. accel = v' =
+// (x' x'' + y' y'') / v, steer = atan(psi' h / max(v, v_floor)) (the kinematic
+// relation of Sec. III), clearance = min over samples and obstacles of
+// sqrt((dx/a)^2 + (dy/b)^2) with constant-velocity predictions (< 1: inside an
+// obstacle ellipse, eq. 1e).
+__global__ void k_controls(ControlArgs A) {
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (s >= A.n_scenes) return;
+  const int b = A.best[s];
+  const int sid = A.shape_id[s];
+  const int g0 = A.goal_off[s], g1 = A.goal_off[s + 1];
+  const bool bad = sid < 0 || sid >= A.n_shapes || b < 0 || g0 + b >= g1 || g0 + b >= A.n_goals;
+  float* acc = A.accel + (size_t)s * A.stride;
+  float* st = A.steer + (size_t)s * A.stride;
+  if (bad) {
+    if (lane == 0) A.clearance[s] = __builtin_nanf("");
+    return;
+  }
+  const ShapeDesc sd = A.shapes[sid];
+  const float* T = A.tables + sd.table_off;
+  const int n = sd.n, NG = A.n_goals, g = g0 + b;
+  const int o0 = A.obs_off[s], m = A.obs_off[s + 1] - o0;
+  const float dt = sd.t_f / (float)(n - 1);
+  float cx[NC], cy[NC], cp[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    cx[k] = A.c[(0 * NC + k) * NG + g];
+    cy[k] = A.c[(1 * NC + k) * NG + g];
+    cp[k] = A.c[(2 * NC + k) * NG + g];
+  }
+  float clear = __builtin_inff();
+  for (int t = lane; t < n && t < A.stride; t += WAVE) {
+    float x = 0.f, y = 0.f, xd = 0.f, yd = 0.f, xdd = 0.f, ydd = 0.f, pd = 0.f;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const float p = T[tab_basis(n, 0) + k * n + t], q = T[tab_basis(n, 1) + k * n + t],
+                  r = T[tab_basis(n, 2) + k * n + t];
+      x = fmaf(p, cx[k], x);
+      y = fmaf(p, cy[k], y);
+      xd = fmaf(q, cx[k], xd);
+      yd = fmaf(q, cy[k], yd);
+      xdd = fmaf(r, cx[k], xdd);
+      ydd = fmaf(r, cy[k], ydd);
+      pd = fmaf(q, cp[k], pd);
+    }
+    const float v = sqrtf(fmaf(xd, xd, yd * yd));
+    acc[t] = v > 0.f ? fmaf(xd, xdd, yd * ydd) / v : 0.f;
+    st[t] = atanf(pd * A.wheelbase / fmaxf(v, A.v_floor));
+    const float tm = (float)t * dt;
+    for (int j = 0; j < m; ++j) {
+      const float* o = A.obs + 4 * (o0 + j);
+      const float dx = (x - fmaf(o[2], tm, o[0])) / A.a, dy = (y - fmaf(o[3], tm, o[1])) / A.b;
+      clear = fminf(clear, sqrtf(fmaf(dx, dx, dy * dy)));
+    }
+  }
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) clear = fminf(clear, __shfl_xor(clear, d, WAVE));
+  if (lane == 0) A.clearance[s] = clear;
+}
+
 __global__ void k_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < n_scenes) {
@@ -150,6 +212,12 @@ __global__ void k_converge_check(const int32_t* __restrict__ goal_off, const flo
 }
 
 }  // namespace
+
+hipError_t launch_controls(const ControlArgs& a, hipStream_t stream) {
+  if (a.n_scenes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_controls, dim3(a.n_scenes), dim3(WAVE), 0, stream, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes, hipStream_t stream) {
   if (n_scenes <= 0) return hipSuccess;

@@ -80,7 +80,7 @@ MLP_EXPORTS = ("traj_mlp_param_count", "traj_mlp_sync_bf16", "traj_features", "t
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
-           "traj_work_ints", "traj_converge", "traj_debug_atan2")
+           "traj_work_ints", "traj_converge", "traj_debug_atan2", "traj_controls")
 
 _lib = None
 
@@ -103,6 +103,7 @@ def lib():
     L.traj_debug_table_size.argtypes = [vp, i32]
     L.traj_debug_reduce.argtypes = [vp, vp, i32, vp]
     L.traj_debug_atan2.argtypes = [vp, vp, vp, i32, vp]
+    L.traj_controls.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), vp, f32, i32, vp, vp, vp, vp]
     L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -297,6 +298,19 @@ class Solver:
         mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl))
         _check(lib().traj_score(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), _ptr(cost),
                                 _ptr(best), _stream(stream)))
+
+    def controls(self, batch: DeviceBatch, state: DeviceState, best, wheelbase=2.5, stride=None, stream=None):
+        """(accel [S][stride], steer [S][stride], clearance [S]) of each scene's chosen trajectory."""
+        import torch
+        stride = stride or max(n for n, _, _ in self.shapes)
+        S_ = max(batch.n_scenes, 1)
+        acc = torch.zeros(S_, stride, device=state.c.device)
+        steer = torch.zeros(S_, stride, device=state.c.device)
+        clear = torch.zeros(S_, device=state.c.device)
+        _check(lib().traj_controls(self.handle, ctypes.byref(batch.c_struct()), ctypes.byref(state.c_struct()),
+                                   _ptr(best), float(wheelbase), int(stride), _ptr(acc), _ptr(steer), _ptr(clear),
+                                   _stream(stream)))
+        return acc, steer, clear
 
     def operators(self, shape: int):
         """FP64 KKT inverses [5, 17, 17] and the FP32 table of one shape (host arrays)."""
