@@ -385,3 +385,71 @@ def controls(prob, obs, c_x, c_y, c_psi, wheelbase, v_floor):
     xi_y = obs[:, 1][None, :] + obs[:, 3][None, :] * t[:, None]
     du = np.sqrt(((x[:, None] - xi_x) / prob.a) ** 2 + ((y[:, None] - xi_y) / prob.b) ** 2)
     return accel, steer, float(du.min())
+
+
+# ------------------------------------------------------------ closed loop (receding horizon)
+#
+# One cycle of the receding-horizon use of the planner (Sec. IV: plan, execute
+# the start of the chosen trajectory, plan again), on a straight road whose
+# traffic follows the Intelligent Driver Model (Treiber, Hennecke and Helbing,
+# Phys. Rev. E 62, 2000; its parameters are not given by the paper and are
+# chosen here). The cycle period is one sample interval t_f / (n - 1).
+
+IDM_DEFAULTS = dict(a=1.0, b=1.5, s0=2.0, T=1.5, delta=4.0, length=4.5, lane_width=3.5)
+
+
+def mpc_goals(ego, n_lanes=4, per_lane=64, t_f=10.0, v_floor=5.0, lane_width=3.5):
+    """Template goals from the current ego state: lane centres x (ego x + max(|v|,
+    v_floor) t_f linspace(0.8, 1.2, per_lane)), lane-major."""
+    ego = np.asarray(ego, np.float64)
+    v = max(np.hypot(ego[2], ego[3]), v_floor)
+    centres = (np.arange(n_lanes) - (n_lanes - 1) // 2) * lane_width
+    fr = np.linspace(0.8, 1.2, per_lane)
+    g = np.zeros((n_lanes * per_lane, 2))
+    for k in range(n_lanes):
+        g[k * per_lane:(k + 1) * per_lane, 0] = ego[0] + v * t_f * fr
+        g[k * per_lane:(k + 1) * per_lane, 1] = centres[k]
+    return g
+
+
+def idm_accel(v, v_des, gap, dv, p):
+    """IDM acceleration; gap = None for a free road."""
+    free = 1.0 - (v / v_des) ** p["delta"]
+    if gap is None:
+        return p["a"] * free
+    s_star = p["s0"] + v * p["T"] + v * dv / (2.0 * np.sqrt(p["a"] * p["b"]))
+    return p["a"] * (free - (max(s_star, 0.0) / gap) ** 2)
+
+
+def idm_step(obs, ego, v_des, dt, p):
+    """Obstacles after one period: each follows the nearest vehicle ahead in its
+    lane (obstacles and the ego; same lane: |dy| < lane width / 2), bumper gap
+    x_lead - x - length (at least 0.1 m); speed clipped at 0, ballistic position
+    update. Lateral positions and velocities are kept."""
+    obs = np.asarray(obs, np.float64).reshape(-1, 4)
+    veh = np.vstack([obs[:, :4], np.asarray(ego, np.float64)[None, :4]])
+    out = obs.copy()
+    for j in range(obs.shape[0]):
+        x, y, v = obs[j, 0], obs[j, 1], obs[j, 2]
+        lead = None
+        for i in range(veh.shape[0]):
+            if i == j or abs(veh[i, 1] - y) >= p["lane_width"] / 2 or veh[i, 0] <= x:
+                continue
+            if lead is None or veh[i, 0] < veh[lead, 0]:
+                lead = i
+        if lead is None:
+            acc = idm_accel(v, v_des[j], None, 0.0, p)
+        else:
+            gap = max(veh[lead, 0] - x - p["length"], 0.1)
+            acc = idm_accel(v, v_des[j], gap, v - veh[lead, 2], p)
+        v_new = max(v + acc * dt, 0.0)
+        out[j, 0] = x + 0.5 * (v + v_new) * dt
+        out[j, 2] = v_new
+    return out
+
+
+def ego_advance(prob, c_x, c_y, c_psi):
+    """Ego state one sample into the chosen trajectory: (x, y, x', y', x'', y'', psi, psi')."""
+    i = 1
+    return np.array([prob.P[i] @ c_x, prob.P[i] @ c_y, prob.Pd[i] @ c_x, prob.Pd[i] @ c_y, prob.Pdd[i] @ c_x,
+                     prob.Pdd[i] @ c_y, prob.P[i] @ c_psi, prob.Pd[i] @ c_psi])
