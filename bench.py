@@ -190,6 +190,37 @@ def run_warmstart(args):
     }
 
 
+def run_mpc(args):
+    """Closed loop: E episodes (4 lanes, 10 IDM vehicles each) replanned every cycle
+    (goal template, solve to residual 1e-3 with at most --iters iterations, scoring,
+    IDM traffic step); timed over --steps cycles after --warmup cycles."""
+    import torch
+
+    from paper_2109_10392_amd import mpc
+    torch.cuda.set_device(0)
+    cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters)
+    for _ in range(args.warmup):
+        cl.cycle()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        cl.cycle()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    m = cl.metrics(args.warmup + args.steps)
+    return {
+        "metric": "closed-loop episode-cycles/s", "value": args.episodes / (ms / 1e3), "unit": "episode-cycles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"closed loop: {args.episodes} episodes, 4 lanes, 10 IDM vehicles each, 256 goals "
+                               f"per plan, replanning every sample interval (0.101 s), at most {args.iters} "
+                               f"iterations per plan (stop at residual 1e-3)", "episodes": args.episodes},
+        "closed_loop": m,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +237,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--group", type=int, default=None, help="goals per matrix-core workgroup")
     ap.add_argument("--waves", type=int, default=None, choices=[1, 2], help="wave kernel: wavefronts per goal")
-    ap.add_argument("--workload", choices=["dense", "uneven", "warmstart"], default="dense")
+    ap.add_argument("--workload", choices=["dense", "uneven", "warmstart", "mpc"], default="dense")
+    ap.add_argument("--episodes", type=int, default=1024, help="mpc: episodes run together")
     ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")
     ap.add_argument("--test-scenes", type=int, default=2048, help="warmstart: held-out scenes timed")
     ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
@@ -219,6 +251,9 @@ def main():
 
     if args.workload == "warmstart":
         print(json.dumps(run_warmstart(args)), flush=True)
+        return
+    if args.workload == "mpc":
+        print(json.dumps(run_mpc(args)), flush=True)
         return
 
     import torch

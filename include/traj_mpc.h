@@ -1,0 +1,78 @@
+/*
+ * traj_mpc.h -- receding-horizon (closed-loop) use of the batched planner of
+ * traj.h, for many episodes at once on straight multi-lane roads.
+ *
+ * The paper (arXiv 2109.10392, Sec. IV) runs the planner in a loop: plan from
+ * the current state, execute the start of the chosen trajectory, plan again,
+ * among traffic. Here a cycle is one sample interval t_f / (n_time - 1) of the
+ * episode's shape: the ego moves to the chosen trajectory's state one sample
+ * ahead, and the other vehicles move by the Intelligent Driver Model (Treiber,
+ * Hennecke and Helbing, 2000; the paper gives no traffic model, so its
+ * parameters are inputs). The frame is re-centred on the ego every cycle (ego x
+ * = 0; the distance is accumulated), so positions stay small.
+ *
+ * A cycle on the caller's stream: traj_mpc_goals -> traj_converge (or
+ * traj_solve_batch) -> traj_score -> traj_mpc_step. Conventions as in traj.h.
+ */
+#ifndef TRAJ_MPC_H
+#define TRAJ_MPC_H
+
+#include <stdint.h>
+
+#include "traj.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float idm_a;        /* IDM maximum acceleration (m/s^2), > 0 */
+  float idm_b;        /* IDM comfortable deceleration (m/s^2), > 0 */
+  float idm_s0;       /* IDM minimum gap (m), >= 0 */
+  float idm_T;        /* IDM time headway (s), >= 0 */
+  float idm_delta;    /* IDM acceleration exponent, > 0 */
+  float car_length;   /* bumper-to-bumper gap = leader x - follower x - car_length (m) */
+  float lane_width;   /* lane centres (k - floor((n_lanes - 1) / 2)) lane_width; same lane: |dy| < lane_width / 2 */
+  int32_t n_lanes;    /* goal template: lanes */
+  int32_t per_lane;   /* goal template: longitudinal slots per lane */
+  float goal_v_floor; /* goal template: x_f = x0 + max(|v|, goal_v_floor) t_f linspace(0.8, 1.2, per_lane) */
+} traj_mpc_params;
+
+/* Episode state, device arrays; ego, obs and goal are the arrays the traj_batch
+ * of the episodes points to. */
+typedef struct {
+  float *ego;          /* [S][8]: x, y, vx, vy, ax, ay, psi, psi' (advanced in place) */
+  float *obs;          /* [n_obs][4]: x, y, vx, vy (advanced in place) */
+  float *goal;         /* [n_goals][2] (rewritten by traj_mpc_goals) */
+  const float *v_des;  /* [n_obs]: IDM desired speed of every obstacle, > 0 */
+  float *obs_next;     /* [n_obs][4] scratch */
+  float *travelled;    /* [S]: distance the ego moved along x (accumulated) */
+  int32_t *collisions; /* [S]: obstacle-ellipse overlaps after each cycle (accumulated) */
+  int32_t *fallbacks;  /* [S]: cycles in which every goal was filtered (accumulated) */
+} traj_episodes;
+
+/*
+ * traj_mpc_goals -- the goal template from every ego's current state
+ * (n_lanes x per_lane goals per episode, lane-major). Episodes with another
+ * goal count are left unchanged.
+ */
+int traj_mpc_goals(void *handle, const traj_batch *batch, const traj_episodes *eps, const traj_mpc_params *p,
+                   void *stream);
+
+/*
+ * traj_mpc_step -- one cycle after planning: every obstacle one period ahead by
+ * IDM (following the nearest vehicle ahead in its lane, the ego included; free
+ * road otherwise; speed clipped at 0, ballistic position update); the ego to its
+ * chosen trajectory one sample ahead (state c of goal best[s]; with best[s] < 0
+ * it holds its heading and brakes at a_max); then the frame re-centred on the
+ * ego and overlaps of obstacle ellipses with the ego centre counted.
+ *   n_obs: total obstacles of the batch (= obs_off[n_scenes]).
+ */
+int traj_mpc_step(void *handle, const traj_batch *batch, const traj_state *state, const int32_t *best,
+                  const traj_episodes *eps, const traj_mpc_params *p, int n_obs, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAJ_MPC_H */

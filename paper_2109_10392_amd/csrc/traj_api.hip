@@ -448,3 +448,18 @@ int traj_debug_reduce(const float* in, float* out, int r, void* stream) {
 }
 
 }  // extern "C"
+
+namespace traj {
+int handle_view(void* handle, const ShapeDesc** shapes, const float** tables, int* n_shapes, float* a_max,
+                float* ell_a, float* ell_b) {
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  *shapes = h->d_shapes;
+  *tables = h->d_tables;
+  *n_shapes = (int)h->shapes.size();
+  *a_max = h->p.a_max;
+  *ell_a = h->p.a;
+  *ell_b = h->p.b;
+  return TRAJ_OK;
+}
+}  // namespace traj

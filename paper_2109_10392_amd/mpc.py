@@ -1,0 +1,131 @@
+"""Closed-loop (receding-horizon) driver: binding of include/traj_mpc.h and a
+batched episode runner.
+
+Every cycle, for all episodes at once on the GPU: place the goal template from
+the ego's current state (traj_mpc_goals), solve to the stopping rule with at
+most `iters` iterations (traj_converge; optionally from the learned warm start),
+rank (traj_score), then move the ego one sample into its chosen trajectory and
+the traffic one period by IDM (traj_mpc_step). The host only launches.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import scenes as S
+from . import traj as T
+
+
+class MpcParams(ctypes.Structure):
+    _fields_ = [("idm_a", ctypes.c_float), ("idm_b", ctypes.c_float), ("idm_s0", ctypes.c_float),
+                ("idm_T", ctypes.c_float), ("idm_delta", ctypes.c_float), ("car_length", ctypes.c_float),
+                ("lane_width", ctypes.c_float), ("n_lanes", ctypes.c_int32), ("per_lane", ctypes.c_int32),
+                ("goal_v_floor", ctypes.c_float)]
+
+
+class EpisodesC(ctypes.Structure):
+    _fields_ = [("ego", ctypes.c_void_p), ("obs", ctypes.c_void_p), ("goal", ctypes.c_void_p),
+                ("v_des", ctypes.c_void_p), ("obs_next", ctypes.c_void_p), ("travelled", ctypes.c_void_p),
+                ("collisions", ctypes.c_void_p), ("fallbacks", ctypes.c_void_p)]
+
+
+# IDM parameters (Treiber, Hennecke and Helbing 2000: typical highway values)
+IDM = dict(idm_a=1.0, idm_b=1.5, idm_s0=2.0, idm_T=1.5, idm_delta=4.0, car_length=4.5, lane_width=3.5)
+
+
+def params(n_lanes=4, per_lane=64, goal_v_floor=5.0, **over):
+    p = dict(IDM, **over)
+    return MpcParams(p["idm_a"], p["idm_b"], p["idm_s0"], p["idm_T"], p["idm_delta"], p["car_length"],
+                     p["lane_width"], n_lanes, per_lane, goal_v_floor)
+
+
+def _bind():
+    L = T.lib()
+    if getattr(L, "_mpc_bound", False):
+        return L
+    vp, i32 = ctypes.c_void_p, ctypes.c_int
+    L.traj_mpc_goals.argtypes = [vp, ctypes.POINTER(T.BatchC), ctypes.POINTER(EpisodesC), ctypes.POINTER(MpcParams),
+                                 vp]
+    L.traj_mpc_step.argtypes = [vp, ctypes.POINTER(T.BatchC), ctypes.POINTER(T.StateC), vp,
+                                ctypes.POINTER(EpisodesC), ctypes.POINTER(MpcParams), i32, vp]
+    L.traj_mpc_goals.restype = ctypes.c_int
+    L.traj_mpc_step.restype = ctypes.c_int
+    L._mpc_bound = True
+    return L
+
+
+class ClosedLoop:
+    """Episodes on 4-lane roads with 10 vehicles each (the template scenes), driven
+    by the planner every cycle."""
+
+    def __init__(self, seeds, tile=("group", 16, True, 1), precision="fp32", iters=100, tol=1e-3, net=None):
+        import torch
+        self.L = _bind()
+        self.batch = S.Batch([S.make_template_scene(int(s)) for s in seeds])
+        self.shape = (100, 10.0, 10)
+        self.solver = T.Solver(S.DEFAULT_PARAMS, [self.shape])
+        self.solver.set_tile(*tile)
+        self.db = T.DeviceBatch.from_batch(self.batch, shapes=[self.shape])
+        self.st = T.DeviceState.empty(self.batch.n_goals)
+        n_s, n_o = self.batch.n_scenes, int(self.batch.obs_off()[-1])
+        self.n_obs = n_o
+        z = lambda *s, dt=torch.float32: torch.zeros(*s, device="cuda", dtype=dt)
+        # IDM desired speed of every vehicle: its initial speed
+        self.v_des = self.db.obs[:, 2].clone()
+        self.obs_next = z(max(n_o, 1), 4)
+        self.travelled, self.collisions, self.fallbacks = z(n_s), z(n_s, dt=torch.int32), z(n_s, dt=torch.int32)
+        self.v_ref = self.db.ego[:, 2].clone()  # cruise speed of the meta-cost: the initial speed
+        self.cost, self.best = z(self.batch.n_goals), z(n_s, dt=torch.int32)
+        self.its = z(n_s, dt=torch.int32)
+        self.p = params()
+        self.precision, self.iters, self.tol, self.net = precision, iters, tol, net
+        self.iters_total = z(n_s, dt=torch.int32)
+
+    def episodes(self):
+        return EpisodesC(T._ptr(self.db.ego), T._ptr(self.db.obs), T._ptr(self.db.goal), T._ptr(self.v_des),
+                         T._ptr(self.obs_next), T._ptr(self.travelled), T._ptr(self.collisions),
+                         T._ptr(self.fallbacks))
+
+    def goals(self):
+        T._check(self.L.traj_mpc_goals(self.solver.handle, ctypes.byref(self.db.c_struct()),
+                                       ctypes.byref(self.episodes()), ctypes.byref(self.p), T._stream(None)))
+
+    def plan(self):
+        if self.net is None:
+            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its, max_iters=self.iters,
+                                 chunk=5, tol=self.tol, precision=self.precision)
+        else:
+            from . import warmstart as W
+            net, mean, std = self.net
+            x = W.features(self.db)
+            import torch
+            acts = torch.empty(net.acts_size(self.db.n_scenes), dtype=torch.int16, device="cuda")
+            y = torch.empty(self.db.n_scenes, net.dims.n_out, device="cuda")
+            net.forward(x, acts, y)
+            W.rows_state(self.db, self.st, y, mean, std)
+            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its,
+                                 max_iters=self.iters, chunk=5, tol=self.tol, from_state=True, fallback=True,
+                                 precision=self.precision)
+        self.iters_total += self.its
+
+    def step(self):
+        T._check(self.L.traj_mpc_step(self.solver.handle, ctypes.byref(self.db.c_struct()),
+                                      ctypes.byref(self.st.c_struct()), T._ptr(self.best),
+                                      ctypes.byref(self.episodes()), ctypes.byref(self.p), self.n_obs,
+                                      T._stream(None)))
+
+    def cycle(self):
+        self.goals()
+        self.plan()
+        self.step()
+
+    def metrics(self, cycles):
+        n = self.batch.n_scenes
+        tr = self.travelled.cpu().numpy()
+        dt = self.shape[1] / (self.shape[0] - 1)
+        return {"episodes": n, "cycles": cycles, "mean_speed": float(tr.mean() / (cycles * dt)),
+                "collision_events": int(self.collisions.sum().item()),
+                "episodes_with_collision": int((self.collisions > 0).sum().item()),
+                "fallback_cycles": int(self.fallbacks.sum().item()),
+                "mean_iterations_per_cycle": float(self.iters_total.float().mean().item()) / max(cycles, 1)}

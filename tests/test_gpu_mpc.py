@@ -1,0 +1,76 @@
+"""Closed loop on the GPU: one cycle against the oracle (goal template, IDM
+traffic, the ego one sample into its chosen trajectory, re-centring, collision
+count), then a short batched run."""
+import numpy as np
+import pytest
+
+from oracle import traj_oracle as O
+from paper_2109_10392_amd import scenes as S
+from tests.test_gpu_parity import PARAMS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_10392_amd import mpc
+    return mpc
+
+
+def test_one_cycle_matches_the_oracle(M):
+    import torch
+    cl = M.ClosedLoop(range(40, 72), iters=30)
+    # perturb the start so the ego is not at rest in its lane and traffic is mixed
+    rng = np.random.default_rng(3)
+    ego = cl.db.ego.cpu().numpy()
+    ego[:, 3] = rng.normal(0, 0.3, ego.shape[0])
+    ego[:, 1] = rng.normal(0, 0.5, ego.shape[0])
+    cl.db.ego.copy_(torch.from_numpy(ego))
+    ego0, obs0 = cl.db.ego.cpu().numpy().astype(np.float64), cl.db.obs.cpu().numpy().astype(np.float64)
+    cl.goals()
+    goals = cl.db.goal.cpu().numpy()
+    cl.plan()
+    torch.cuda.synchronize()
+    c = cl.st.c.cpu().numpy().astype(np.float64)
+    best = cl.best.cpu().numpy()
+    cl.step()
+    torch.cuda.synchronize()
+    ego1, obs1 = cl.db.ego.cpu().numpy(), cl.db.obs.cpu().numpy()
+    tr, col = cl.travelled.cpu().numpy(), cl.collisions.cpu().numpy()
+    prob = O.Problem(100, 10.0, 10, PARAMS)
+    off, ooff = cl.batch.goal_off(), cl.batch.obs_off()
+    v_des = cl.v_des.cpu().numpy().astype(np.float64)
+    p = dict(O.IDM_DEFAULTS)
+    dt = prob.t[1]
+    for s in range(cl.batch.n_scenes):
+        g_ref = O.mpc_goals(ego0[s])
+        assert np.allclose(goals[off[s]:off[s + 1]], g_ref, rtol=1e-6, atol=1e-4), s
+        o_ref = O.idm_step(obs0[ooff[s]:ooff[s + 1]], ego0[s], v_des[ooff[s]:ooff[s + 1]], dt, p)
+        assert best[s] >= 0
+        g = off[s] + best[s]
+        e_ref = O.ego_advance(prob, c[0, :, g], c[1, :, g], c[2, :, g])
+        shift = e_ref[0]
+        assert abs(tr[s] - shift) <= 1e-4 * max(1.0, abs(shift)), s
+        e_ref[0] = 0.0
+        assert np.allclose(ego1[s], e_ref, rtol=1e-4, atol=1e-4), (s, ego1[s], e_ref)
+        o_ref[:, 0] -= shift
+        assert np.allclose(obs1[ooff[s]:ooff[s + 1]], o_ref, rtol=1e-5, atol=1e-4), s
+        dx = o_ref[:, 0] / PARAMS["a"]
+        dy = (o_ref[:, 1] - e_ref[1]) / PARAMS["b"]
+        assert col[s] == int(np.sum(dx * dx + dy * dy < 1.0)), s
+
+
+def test_batched_closed_loop_run(M):
+    import torch
+    cl = M.ClosedLoop(range(64), iters=100)
+    for _ in range(40):
+        cl.cycle()
+    torch.cuda.synchronize()
+    m = cl.metrics(40)
+    print(m)
+    assert np.all(np.isfinite(cl.db.ego.cpu().numpy())) and np.all(np.isfinite(cl.db.obs.cpu().numpy()))
+    assert m["mean_speed"] > 5.0
+    assert 0 < m["mean_iterations_per_cycle"] <= 100
