@@ -198,7 +198,7 @@ def run_mpc(args):
 
     from paper_2109_10392_amd import mpc
     torch.cuda.set_device(0)
-    cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters)
+    cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters, warm=args.warm, clear_min=args.clear_min)
     for _ in range(args.warmup):
         cl.cycle()
     torch.cuda.synchronize()
@@ -216,7 +216,9 @@ def run_mpc(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"closed loop: {args.episodes} episodes, 4 lanes, 10 IDM vehicles each, 256 goals "
                                f"per plan, replanning every sample interval (0.101 s), at most {args.iters} "
-                               f"iterations per plan (stop at residual 1e-3)", "episodes": args.episodes},
+                               f"iterations per plan (stop at residual 1e-3), start: {args.warm}, "
+                               f"collision post-check at {args.clear_min}",
+                   "episodes": args.episodes, "warm": args.warm, "clear_min": args.clear_min},
         "closed_loop": m,
     }
 
@@ -239,6 +241,11 @@ def main():
     ap.add_argument("--waves", type=int, default=None, choices=[1, 2], help="wave kernel: wavefronts per goal")
     ap.add_argument("--workload", choices=["dense", "uneven", "warmstart", "mpc"], default="dense")
     ap.add_argument("--episodes", type=int, default=1024, help="mpc: episodes run together")
+    ap.add_argument("--warm", choices=["cold", "previous", "shifted"], default="shifted",
+                    help="mpc: start of every plan after the first (the previous cycle's solutions advanced by "
+                         "one period, the same unshifted, or the cold start)")
+    ap.add_argument("--clear-min", type=float, default=1.0,
+                    help="mpc: collision post-check of the ranking (scaled obstacle distance; 0 = off)")
     ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")
     ap.add_argument("--test-scenes", type=int, default=2048, help="warmstart: held-out scenes timed")
     ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")

@@ -108,6 +108,10 @@ typedef struct {
   const float *v_ref; /* device [n_scenes]: v_cruise (kind 0) or v_max (kind 1) */
   float w1, w2;       /* weights of eq. 26 (ignored for kind 0) */
   const float *y_rl;  /* device [n_scenes]: lateral position of the right lane (kind 1; may be NULL for kind 0) */
+  float clear_min;    /* collision post-check, 0 = off: a goal whose trajectory comes closer than
+                         clear_min to an obstacle, in the scaled distance sqrt((dx/a)^2 + (dy/b)^2)
+                         of eq. 1e against the constant-velocity predictions, is discarded (cost
+                         +inf); 1 discards every trajectory that enters an obstacle ellipse */
 } traj_metacost;
 
 /*
@@ -151,8 +155,10 @@ int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, i
 /*
  * traj_score -- meta-cost per goal (eq. 25 or 26, v(t) = |(x'(t), y'(t))| of the
  * final coefficients) with the heading post-filter (cost = +inf when
- * max_t |psi(t)| > psi_max, Sec. III assumption 2), then per scene the lowest
- * index attaining the minimum finite cost.
+ * max_t |psi(t)| > psi_max, Sec. III assumption 2) and, if mc->clear_min > 0,
+ * the collision post-check (cost = +inf when the trajectory comes closer than
+ * clear_min to an obstacle), then per scene the lowest index attaining the
+ * minimum finite cost.
  *   cost: device [n_goals]. best: device [n_scenes], index within the scene, -1
  *   if every goal of the scene is filtered.
  * Errors: TRAJ_E_INVAL, TRAJ_E_HIP.

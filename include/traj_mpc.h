@@ -49,6 +49,8 @@ typedef struct {
   float *travelled;    /* [S]: distance the ego moved along x (accumulated) */
   int32_t *collisions; /* [S]: obstacle-ellipse overlaps after each cycle (accumulated) */
   int32_t *fallbacks;  /* [S]: cycles in which every goal was filtered (accumulated) */
+  float *shift;        /* [S]: the ego's x advance in the last traj_mpc_step (the frame's
+                          re-centring; written by traj_mpc_step, read by traj_mpc_shift) */
 } traj_episodes;
 
 /*
@@ -70,6 +72,24 @@ int traj_mpc_goals(void *handle, const traj_batch *batch, const traj_episodes *e
  */
 int traj_mpc_step(void *handle, const traj_batch *batch, const traj_state *state, const int32_t *best,
                   const traj_episodes *eps, const traj_mpc_params *p, int n_obs, void *stream);
+
+/*
+ * traj_mpc_shift -- warm start of the next cycle from this cycle's solutions
+ * (every goal slot's final iterate), advanced by the cycle's period: a
+ * trajectory of the new horizon [dt, t_f + dt] is the same polynomial, so with
+ * u0 = dt / t_f = 1 / (n_time - 1) the Bernstein coefficients of each of
+ * x, y, psi become c' = S c, S_ik = sum_q B(10-i, k-q; u0) B(i, q; 1+u0),
+ * B(n, j; u) = C(n, j) u^j (1-u)^(n-j) (the polar form at u0 (10-i times) and
+ * 1+u0 (i times)), then x' -= shift[s] (the frame re-centring; the basis sums
+ * to one). The multipliers keep their pairing <lambda, c> of eq. 10,
+ * lambda'^T c' = lambda^T S^-1 c', i.e. lambda' = S^-T lambda with
+ * S^-1 = S(-u0). Call after traj_mpc_step and traj_mpc_goals; solve with
+ * TRAJ_INIT_FROM_STATE (and TRAJ_WARM_FALLBACK). The first iteration's x/y step
+ * puts every goal's boundary values in place (eq. 8b).
+ *   state: c and lam, device [3][11][n_goals], updated in place. eps: shift.
+ */
+int traj_mpc_shift(void *handle, const traj_batch *batch, traj_state *state, const traj_episodes *eps,
+                   void *stream);
 
 #ifdef __cplusplus
 }

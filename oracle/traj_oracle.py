@@ -329,12 +329,15 @@ def solve(prob, ego, obs, goals, iters, init=None, record=False):
 # ------------------------------------------------------------ ranking (Sec. III-F)
 
 
-def meta_cost(prob, c_x, c_y, c_psi, kind=0, v_ref=None, w1=1.0, w2=1.0, y_rl=0.0):
+def meta_cost(prob, c_x, c_y, c_psi, kind=0, v_ref=None, w1=1.0, w2=1.0, y_rl=0.0, obs=None, clear_min=0.0):
     """Meta-cost per goal: eq. 25 (kind 0, v_ref = v_cruise) or eq. 26 (kind 1, v_ref = v_max).
 
     v(t) is the speed of the final trajectory, sqrt(x'^2 + y'^2). A goal whose
     heading P c_psi exceeds psi_max in magnitude at any sample is discarded
-    (cost +inf), the post-filter of Sec. III.
+    (cost +inf), the post-filter of Sec. III. With clear_min > 0, a goal whose
+    trajectory comes closer than clear_min to an obstacle (the clearance of
+    `controls`: scaled distance of eq. 1e to the constant-velocity predictions
+    of assumption 3) is discarded too.
     """
     v = np.sqrt((prob.Pd @ c_x) ** 2 + (prob.Pd @ c_y) ** 2)
     if kind == 0:
@@ -344,6 +347,11 @@ def meta_cost(prob, c_x, c_y, c_psi, kind=0, v_ref=None, w1=1.0, w2=1.0, y_rl=0.
         cost = np.sum(w1 * (v - v_ref) ** 2 + w2 * (y - y_rl) ** 2, axis=0)
     psi = prob.P @ c_psi
     bad = np.max(np.abs(psi), axis=0) > prob.psi_max
+    if clear_min > 0.0 and obs is not None and np.asarray(obs).size > 0:
+        c_x2, c_y2, c_p2 = (np.asarray(u, np.float64).reshape(prob.N, -1) for u in (c_x, c_y, c_psi))
+        clear = np.array([controls(prob, obs, c_x2[:, i], c_y2[:, i], c_p2[:, i], 1.0, 1.0)[2]
+                          for i in range(c_x2.shape[1])])
+        bad = bad | ~(clear >= clear_min)
     return np.where(bad, np.inf, cost)
 
 
@@ -446,6 +454,39 @@ def idm_step(obs, ego, v_des, dt, p):
         out[j, 0] = x + 0.5 * (v + v_new) * dt
         out[j, 2] = v_new
     return out
+
+
+def shift_matrix(n_coef, u0):
+    """S with c' = S c: the Bernstein coefficients, on [0, 1], of the polynomial
+    u -> sum_k c_k B_k(u0 + u), i.e. the same trajectory seen from a horizon that
+    starts u0 t_f later. Found by collocation: both sides agree at n_coef
+    distinct points of [0, 1], which fixes a polynomial of degree n_coef - 1."""
+    deg = n_coef - 1
+    nodes = np.linspace(0.0, 1.0, n_coef)
+
+    def basis(u):
+        return np.stack([comb(deg, k) * u ** k * (1.0 - u) ** (deg - k) for k in range(n_coef)], axis=1)
+
+    return np.linalg.solve(basis(nodes), basis(nodes + u0))
+
+
+def shift_solution(c, lam, u0, dx):
+    """Warm start of the next receding-horizon cycle from this cycle's solution.
+
+    c, lam: (3, n_coef, G) coefficients and multipliers of x, y, psi. Returns
+    (c', lam'): c' = S c per axis with x' shifted by -dx (the frame moved dx
+    forward; Bernstein polynomials sum to one, so a constant moves every
+    coefficient), and lam' = S^-T lam, which keeps lam'^T S c = lam^T c: the
+    multiplier term <lambda, c> of the augmented cost (eq. 10) pairs with the same
+    trajectory as before.
+    """
+    c = np.asarray(c, np.float64)
+    lam = np.asarray(lam, np.float64)
+    Smat = shift_matrix(c.shape[1], u0)
+    c_new = np.einsum("ik,akg->aig", Smat, c)
+    c_new[0] -= np.asarray(dx, np.float64)
+    lam_new = np.stack([np.linalg.solve(Smat.T, lam[a]) for a in range(3)])
+    return c_new, lam_new
 
 
 def ego_advance(prob, c_x, c_y, c_psi):

@@ -305,6 +305,8 @@ int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, cons
   if (state == nullptr || mc == nullptr) return fail(TRAJ_E_INVAL, "state / metacost is NULL");
   if (mc->kind != 0 && mc->kind != 1) return fail(TRAJ_E_INVAL, "metacost kind must be 0 or 1");
   if (!isfinite(mc->w1) || !isfinite(mc->w2)) return fail(TRAJ_E_INVAL, "metacost weights must be finite");
+  if (!(isfinite(mc->clear_min) && mc->clear_min >= 0.f))
+    return fail(TRAJ_E_INVAL, "metacost clear_min must be finite and >= 0");
   if (batch->n_scenes == 0) return TRAJ_OK;
   if (mc->v_ref == nullptr || (mc->kind == 1 && mc->y_rl == nullptr))
     return fail(TRAJ_E_INVAL, "metacost reference arrays are NULL");
@@ -325,6 +327,11 @@ int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, cons
   a.w1 = mc->w1;
   a.w2 = mc->w2;
   a.psi_max = h->p.psi_max;
+  a.obs_off = batch->obs_off;
+  a.obs = batch->obs;
+  a.a = h->p.a;
+  a.b = h->p.b;
+  a.clear_min = mc->clear_min;
   a.cost = cost;
   a.best = best;
   hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream);

@@ -114,6 +114,10 @@ struct ScoreArgs {
   const float* v_ref;
   const float* y_rl;
   float w1, w2, psi_max;
+  // collision post-check (clear_min > 0): obstacles of the batch and the ellipse axes
+  const int32_t* obs_off;
+  const float* obs;
+  float a, b, clear_min;
   float* cost;
   int32_t* best;
 };

@@ -7,7 +7,9 @@
 //                    following the nearest vehicle ahead in its lane
 //   k_mpc_ego        the ego one sample into its chosen trajectory (or a
 //                    braking fallback when every goal was filtered), then the
-//                    frame re-centred on the ego and collisions counted.
+//                    frame re-centred on the ego and collisions counted
+//   k_mpc_shift      every goal's solution advanced by one period: the warm
+//                    start of the next cycle.
 // The period is one sample interval t_f / (n - 1) of the episode's shape.
 #include "traj_internal.h"
 #include "traj_mpc.h"
@@ -164,6 +166,7 @@ __global__ void k_mpc_ego(MpcArgs A) {
   ne[0] = 0.f;
   for (int q = 0; q < 8; ++q) e[q] = ne[q];
   A.e.travelled[s] += shift;
+  A.e.shift[s] = shift;
   int hits = 0;
   for (int o = A.obs_off[s]; o < A.obs_off[s + 1]; ++o) {
     const float* src = A.e.obs_next + 4 * o;
@@ -176,6 +179,73 @@ __global__ void k_mpc_ego(MpcArgs A) {
     hits += fmaf(dx, dx, dy * dy) < 1.f;
   }
   A.e.collisions[s] += hits;
+}
+
+// Bernstein coefficients of degree NC-1 re-expressed on the interval shifted by
+// u0 (the polar form of the polynomial at u0 and 1+u0):
+//   S_ik = sum_q B(NC-1-i, k-q; u0) B(i, q; 1+u0),  B(n, j; u) = C(n, j) u^j (1-u)^(n-j).
+// Entry e = i * NC + k. FP64: the terms alternate in sign for 1+u0 > 1.
+__device__ double binom(int n, int j) {
+  double r = 1.0;
+  for (int m = 1; m <= j; ++m) r = r * (double)(n - j + m) / (double)m;
+  return r;
+}
+
+__device__ double shift_entry(int e, double u0) {
+  const int i = e / NC, k = e - i * NC, deg = NC - 1;
+  const double a = u0, b = 1.0 + u0;
+  double acc = 0.0;
+  for (int q = 0; q <= i && q <= k; ++q) {
+    const int p = k - q, na = deg - i;
+    if (p > na) continue;
+    double ta = binom(na, p), tb = binom(i, q);
+    for (int r = 0; r < p; ++r) ta *= a;
+    for (int r = 0; r < na - p; ++r) ta *= 1.0 - a;
+    for (int r = 0; r < q; ++r) tb *= b;
+    for (int r = 0; r < i - q; ++r) tb *= 1.0 - b;
+    acc += ta * tb;
+  }
+  return acc;
+}
+
+// One workgroup per episode: S(u0) and S(-u0) of the episode's shape in LDS,
+// then every goal's (c, lambda) of the three axes advanced (threads over goals;
+// the goal-fastest layout makes each coefficient load and store coalesced).
+__global__ __launch_bounds__(256) void k_mpc_shift(MpcArgs A, float* c, float* lam) {
+  __shared__ float fwd[NC * NC], inv[NC * NC];
+  const int s = blockIdx.x;
+  const int sid = A.shape_id[s];
+  if (sid < 0 || sid >= A.n_shapes) return;
+  const ShapeDesc sd = A.shapes[sid];
+  const double u0 = 1.0 / (double)(sd.n - 1);
+  const int t = threadIdx.x;
+  if (t < NC * NC) fwd[t] = (float)shift_entry(t, u0);
+  if (t >= 128 && t - 128 < NC * NC) inv[t - 128] = (float)shift_entry(t - 128, -u0);
+  __syncthreads();
+  const int g0 = max(A.goal_off[s], 0), g1 = min(A.goal_off[s + 1], A.n_goals);
+  const float dx = A.e.shift[s];
+  const int NG = A.n_goals;
+  for (int g = g0 + t; g < g1; g += blockDim.x) {
+    for (int ax = 0; ax < 3; ++ax) {
+      float v[NC], w[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        v[k] = c[(ax * NC + k) * NG + g];
+        w[k] = lam[(ax * NC + k) * NG + g];
+      }
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        float cv = 0.f, lv = 0.f;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          cv = fmaf(fwd[i * NC + k], v[k], cv);  // (S c)_i
+          lv = fmaf(inv[k * NC + i], w[k], lv);  // (S(-u0)^T lambda)_i
+        }
+        c[(ax * NC + i) * NG + g] = ax == 0 ? cv - dx : cv;
+        lam[(ax * NC + i) * NG + g] = lv;
+      }
+    }
+  }
 }
 
 bool params_ok(const traj_mpc_params* p) {
@@ -233,7 +303,7 @@ int traj_mpc_step(void* handle, const traj_batch* batch, const traj_state* state
   if (batch == nullptr || state == nullptr || state->c == nullptr || best == nullptr || eps == nullptr ||
       !params_ok(p) || eps->ego == nullptr || eps->obs == nullptr || eps->v_des == nullptr ||
       eps->obs_next == nullptr || eps->travelled == nullptr || eps->collisions == nullptr ||
-      eps->fallbacks == nullptr || n_obs < 0)
+      eps->fallbacks == nullptr || eps->shift == nullptr || n_obs < 0)
     return traj::api_fail(TRAJ_E_INVAL, "traj_mpc_step: bad arguments");
   MpcArgs a = {};
   int rc = fill(handle, batch, &a);
@@ -252,6 +322,22 @@ int traj_mpc_step(void* handle, const traj_batch* batch, const traj_state* state
     e = hipGetLastError();
   }
   return e == hipSuccess ? TRAJ_OK : traj::api_fail(TRAJ_E_HIP, "traj_mpc_step: %s", hipGetErrorString(e));
+}
+
+int traj_mpc_shift(void* handle, const traj_batch* batch, traj_state* state, const traj_episodes* eps,
+                   void* stream) {
+  if (batch == nullptr || state == nullptr || state->c == nullptr || state->lam == nullptr || eps == nullptr ||
+      eps->shift == nullptr)
+    return traj::api_fail(TRAJ_E_INVAL, "traj_mpc_shift: bad arguments");
+  MpcArgs a = {};
+  int rc = fill(handle, batch, &a);
+  if (rc != TRAJ_OK) return rc;
+  a.e = *eps;
+  if (batch->n_scenes == 0 || batch->n_goals == 0) return TRAJ_OK;
+  hipLaunchKernelGGL(k_mpc_shift, dim3(batch->n_scenes), dim3(256), 0, (hipStream_t)stream, a, state->c,
+                     state->lam);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TRAJ_OK : traj::api_fail(TRAJ_E_HIP, "traj_mpc_shift: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -1,6 +1,8 @@
 // Meta-cost ranking (Sec. III-F): eq. 25 (cruise) or eq. 26 (high speed close
 // to the right lane) per goal, the heading post-filter of Sec. III (assumption
-// 2: discard |psi| beyond psi_max), then the lowest-index argmin per scene.
+// 2: discard |psi| beyond psi_max), optionally a collision post-check against
+// the constant-velocity obstacle predictions (assumption 3), then the
+// lowest-index argmin per scene.
 #include "traj_internal.h"
 
 namespace traj {
@@ -56,17 +58,28 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
   }
   const float vref = A.v_ref[s];
   const float yrl = (A.kind == 1 && A.y_rl != nullptr) ? A.y_rl[s] : 0.f;
-  float acc = 0.f, pmax = 0.f;
+  const bool check = A.clear_min > 0.f;
+  const int o0 = check ? A.obs_off[s] : 0, m = check ? A.obs_off[s + 1] - o0 : 0;
+  const float dt = sd.t_f / (float)(n - 1);
+  float acc = 0.f, pmax = 0.f, clear = __builtin_inff();
   for (int t = lane; t < n; t += WAVE) {
-    float xd = 0.f, yd = 0.f, y = 0.f, psi = 0.f;
+    float xd = 0.f, yd = 0.f, x = 0.f, y = 0.f, psi = 0.f;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const float p = T[tab_basis(n, 0) + k * n + t];
       const float pd = T[tab_basis(n, 1) + k * n + t];
       xd = fmaf(pd, cx[k], xd);
       yd = fmaf(pd, cy[k], yd);
+      x = fmaf(p, cx[k], x);
       y = fmaf(p, cy[k], y);
       psi = fmaf(p, cp[k], psi);
+    }
+    // squared scaled distance to every obstacle's constant-velocity prediction (eq. 1e)
+    const float tm = (float)t * dt;
+    for (int j = 0; j < m; ++j) {
+      const float* o = A.obs + 4 * (o0 + j);
+      const float dx = (x - fmaf(o[2], tm, o[0])) / A.a, dy = (y - fmaf(o[3], tm, o[1])) / A.b;
+      clear = fminf(clear, fmaf(dx, dx, dy * dy));
     }
     const float v = sqrtf(fmaf(xd, xd, yd * yd));
     const float dv = v - vref;
@@ -80,7 +93,10 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
   }
   acc = wave_sum(acc);
   pmax = wave_max(pmax);
-  if (lane == 0) A.cost[g] = (pmax > A.psi_max) ? __builtin_inff() : acc;
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) clear = fminf(clear, __shfl_xor(clear, d, WAVE));
+  const bool hit = check && !(sqrtf(clear) >= A.clear_min);
+  if (lane == 0) A.cost[g] = (pmax > A.psi_max || hit) ? __builtin_inff() : acc;
 }
 
 // One workgroup per scene: lowest index attaining the minimum finite cost.

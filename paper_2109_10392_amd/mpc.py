@@ -3,9 +3,11 @@ batched episode runner.
 
 Every cycle, for all episodes at once on the GPU: place the goal template from
 the ego's current state (traj_mpc_goals), solve to the stopping rule with at
-most `iters` iterations (traj_converge; optionally from the learned warm start),
-rank (traj_score), then move the ego one sample into its chosen trajectory and
-the traffic one period by IDM (traj_mpc_step). The host only launches.
+most `iters` iterations (traj_converge; from the cold start, the previous
+cycle's solutions, those advanced by one period (traj_mpc_shift) or the learned
+warm start), rank (traj_score, optionally with the collision post-check), then
+move the ego one sample into its chosen trajectory and the traffic one period
+by IDM (traj_mpc_step). The host only launches.
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ class MpcParams(ctypes.Structure):
 class EpisodesC(ctypes.Structure):
     _fields_ = [("ego", ctypes.c_void_p), ("obs", ctypes.c_void_p), ("goal", ctypes.c_void_p),
                 ("v_des", ctypes.c_void_p), ("obs_next", ctypes.c_void_p), ("travelled", ctypes.c_void_p),
-                ("collisions", ctypes.c_void_p), ("fallbacks", ctypes.c_void_p)]
+                ("collisions", ctypes.c_void_p), ("fallbacks", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
 
 
 # IDM parameters (Treiber, Hennecke and Helbing 2000: typical highway values)
@@ -49,20 +51,29 @@ def _bind():
                                  vp]
     L.traj_mpc_step.argtypes = [vp, ctypes.POINTER(T.BatchC), ctypes.POINTER(T.StateC), vp,
                                 ctypes.POINTER(EpisodesC), ctypes.POINTER(MpcParams), i32, vp]
+    L.traj_mpc_shift.argtypes = [vp, ctypes.POINTER(T.BatchC), ctypes.POINTER(T.StateC), ctypes.POINTER(EpisodesC),
+                                 vp]
     L.traj_mpc_goals.restype = ctypes.c_int
     L.traj_mpc_step.restype = ctypes.c_int
+    L.traj_mpc_shift.restype = ctypes.c_int
     L._mpc_bound = True
     return L
 
 
 class ClosedLoop:
-    """Episodes on 4-lane roads with 10 vehicles each (the template scenes), driven
-    by the planner every cycle."""
+    """Episodes on 4-lane roads with 10 vehicles each (headway-respecting traffic
+    around the ego, goals = the template), driven by the planner every cycle."""
 
-    def __init__(self, seeds, tile=("group", 16, True, 1), precision="fp32", iters=100, tol=1e-3, net=None):
+    def __init__(self, seeds, tile=("group", 16, True, 1), precision="fp32", iters=100, tol=1e-3, net=None,
+                 warm="cold", clear_min=0.0):
+        """warm: start of every plan after the first: "cold"; "previous" (the
+        previous cycle's iterate of the same goal slot); "shifted" (that iterate
+        advanced by one period, traj_mpc_shift); or "learned" (the network `net` =
+        (Network, mean, std)). The warm starts keep the cold start as per-goal
+        fallback. clear_min: the collision post-check of the ranking (0 = off)."""
         import torch
         self.L = _bind()
-        self.batch = S.Batch([S.make_template_scene(int(s)) for s in seeds])
+        self.batch = S.Batch([S.make_traffic_scene(int(s)) for s in seeds])
         self.shape = (100, 10.0, 10)
         self.solver = T.Solver(S.DEFAULT_PARAMS, [self.shape])
         self.solver.set_tile(*tile)
@@ -75,26 +86,45 @@ class ClosedLoop:
         self.v_des = self.db.obs[:, 2].clone()
         self.obs_next = z(max(n_o, 1), 4)
         self.travelled, self.collisions, self.fallbacks = z(n_s), z(n_s, dt=torch.int32), z(n_s, dt=torch.int32)
+        self.shift = z(n_s)
         self.v_ref = self.db.ego[:, 2].clone()  # cruise speed of the meta-cost: the initial speed
         self.cost, self.best = z(self.batch.n_goals), z(n_s, dt=torch.int32)
         self.its = z(n_s, dt=torch.int32)
         self.p = params()
         self.precision, self.iters, self.tol, self.net = precision, iters, tol, net
+        if warm not in ("cold", "previous", "shifted", "learned"):
+            raise ValueError(f"unknown warm start {warm!r}")
+        self.warm = warm if net is None else "learned"
+        self.clear_min = float(clear_min)
+        self.cycles_done = 0
         self.iters_total = z(n_s, dt=torch.int32)
 
     def episodes(self):
         return EpisodesC(T._ptr(self.db.ego), T._ptr(self.db.obs), T._ptr(self.db.goal), T._ptr(self.v_des),
                          T._ptr(self.obs_next), T._ptr(self.travelled), T._ptr(self.collisions),
-                         T._ptr(self.fallbacks))
+                         T._ptr(self.fallbacks), T._ptr(self.shift))
 
     def goals(self):
         T._check(self.L.traj_mpc_goals(self.solver.handle, ctypes.byref(self.db.c_struct()),
                                        ctypes.byref(self.episodes()), ctypes.byref(self.p), T._stream(None)))
 
+    def shift_state(self):
+        T._check(self.L.traj_mpc_shift(self.solver.handle, ctypes.byref(self.db.c_struct()),
+                                       ctypes.byref(self.st.c_struct()), ctypes.byref(self.episodes()),
+                                       T._stream(None)))
+
     def plan(self):
-        if self.net is None:
-            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its, max_iters=self.iters,
-                                 chunk=5, tol=self.tol, precision=self.precision)
+        kw = dict(max_iters=self.iters, chunk=5, tol=self.tol, precision=self.precision, clear_min=self.clear_min)
+        if self.warm in ("previous", "shifted") and self.cycles_done > 0:
+            # the previous cycle's (c, lambda) of every goal slot (advanced by one period
+            # for "shifted"); the x/y step of the first iteration enforces the new
+            # boundary values (eq. 8b)
+            if self.warm == "shifted":
+                self.shift_state()
+            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its, from_state=True,
+                                 fallback=True, **kw)
+        elif self.warm != "learned":
+            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its, **kw)
         else:
             from . import warmstart as W
             net, mean, std = self.net
@@ -104,9 +134,8 @@ class ClosedLoop:
             y = torch.empty(self.db.n_scenes, net.dims.n_out, device="cuda")
             net.forward(x, acts, y)
             W.rows_state(self.db, self.st, y, mean, std)
-            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its,
-                                 max_iters=self.iters, chunk=5, tol=self.tol, from_state=True, fallback=True,
-                                 precision=self.precision)
+            self.solver.converge(self.db, self.st, self.v_ref, self.cost, self.best, self.its, from_state=True,
+                                 fallback=True, **kw)
         self.iters_total += self.its
 
     def step(self):
@@ -119,6 +148,7 @@ class ClosedLoop:
         self.goals()
         self.plan()
         self.step()
+        self.cycles_done += 1
 
     def metrics(self, cycles):
         n = self.batch.n_scenes

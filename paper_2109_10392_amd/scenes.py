@@ -18,6 +18,14 @@ these draws stand in for them with the shapes the workloads name):
   (a = 5.6, b = 3.1) contains the ego start is drawn again;
 * goals: goal i targets lane ``i mod n_lanes`` at x_f = v0 * t_f * U(0.8, 1.2).
 
+Closed-loop traffic (``make_traffic_scene``) must also be drivable by the
+traffic model, so vehicles keep headways: obstacles are drawn as above but with
+x ~ U(-40, 120) m (followers behind the ego too), and a draw is rejected unless,
+against every vehicle already placed in its lane (the ego included), the
+bumper-to-bumper gap (centre distance less 4.5 m) is at least
+2 + 1.5 v_rear + max(0, v_rear - v_front)^2 / 6 m (a standstill gap, a 1.5 s
+headway and the distance to shed the closing speed at 3 m/s^2).
+
 Arrays are float32 (what the device path consumes); the oracle promotes them
 to float64 itself.
 """
@@ -147,6 +155,45 @@ def make_template_scene(seed: int, n_obs: int = 10, n_lanes: int = 4, n_time: in
     s = make_scene(seed, n_goals=1, n_obs=n_obs, n_lanes=n_lanes, n_time=n_time, t_f=t_f)
     s.goals = template_goals(float(s.ego[2]), t_f, n_lanes, per_lane)
     return s
+
+
+def make_traffic_scene(seed: int, n_obs: int = 10, n_lanes: int = 4, n_time: int = 100, t_f: float = 10.0,
+                       per_lane: int = 64, x_range=(-40.0, 120.0), v0_range=(10.0, 20.0),
+                       vobs_range=(5.0, 15.0)) -> Scene:
+    """A closed-loop start: headway-respecting traffic around the ego (module recipe),
+    goals = the template. Draw order: v0, then per obstacle attempt (lane, x, vx)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = lane_centres(n_lanes)
+    v0 = rng.uniform(*v0_range)
+    placed = [(0.0, 0.0, v0)]  # (x, y, v), the ego first
+    obs = np.zeros((n_obs, 4), np.float64)
+    for j in range(n_obs):
+        for _attempt in range(10000):
+            lane = int(rng.integers(0, n_lanes))
+            x = rng.uniform(*x_range)
+            vx = rng.uniform(*vobs_range)
+            y = centres[lane]
+            if (x / ELLIPSE_A) ** 2 + (y / ELLIPSE_B) ** 2 < 1.0:
+                continue
+            ok = True
+            for (px, py, pv) in placed:
+                if abs(py - y) >= LANE_WIDTH / 2:
+                    continue
+                (rx, rv), (fx, fv) = ((x, vx), (px, pv)) if x < px else ((px, pv), (x, vx))
+                need = 2.0 + 1.5 * rv + max(0.0, rv - fv) ** 2 / 6.0
+                if fx - rx - 4.5 < need:
+                    ok = False
+                    break
+            if ok:
+                break
+        else:
+            raise RuntimeError(f"traffic scene {seed}: no room for obstacle {j}")
+        placed.append((x, y, vx))
+        obs[j] = (x, y, vx, 0.0)
+    ego = np.array([0.0, 0.0, v0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    return Scene(ego=ego.astype(np.float32), obs=obs.astype(np.float32),
+                 goals=template_goals(v0, t_f, n_lanes, per_lane).astype(np.float32), n_time=n_time, t_f=t_f,
+                 n_lanes=n_lanes, seed=seed)
 
 
 # ---------------------------------------------------------------- workloads

@@ -61,7 +61,7 @@ class TileC(ctypes.Structure):
 
 class MetaC(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("v_ref", ctypes.c_void_p), ("w1", ctypes.c_float),
-                ("w2", ctypes.c_float), ("y_rl", ctypes.c_void_p)]
+                ("w2", ctypes.c_float), ("y_rl", ctypes.c_void_p), ("clear_min", ctypes.c_float)]
 
 
 class MlpDims(ctypes.Structure):
@@ -240,7 +240,7 @@ class Solver:
 
     def converge(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, scene_iters, max_iters=300,
                  chunk=5, tol=1e-3, from_state=False, fallback=False, precision="fp32", kernel="auto", kind=0,
-                 w1=1.0, w2=1.0, y_rl=None, stream=None):
+                 w1=1.0, w2=1.0, y_rl=None, clear_min=0.0, stream=None):
         """Chunked solve until each scene's best goal meets the residual tolerance
         (device-side bookkeeping; state.scene_done and scene_iters hold the outcome)."""
         import torch
@@ -250,7 +250,7 @@ class Solver:
             state.scene_done = torch.zeros(max(batch.n_scenes, 1), dtype=torch.int32, device=state.c.device)
         b = batch.c_struct()
         s = state.c_struct()
-        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl))
+        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl), float(clear_min))
         _check(lib().traj_converge(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), int(max_iters),
                                    int(chunk), float(tol), self._flags(from_state, fallback, precision, kernel),
                                    _ptr(cost), _ptr(best), _ptr(scene_iters), _stream(stream)))
@@ -292,10 +292,10 @@ class Solver:
             state.work = torch.zeros(need, dtype=torch.int32, device=state.c.device)
 
     def score(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, kind=0, w1=1.0, w2=1.0,
-              y_rl=None, stream=None):
+              y_rl=None, clear_min=0.0, stream=None):
         b = batch.c_struct()
         s = state.c_struct()
-        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl))
+        mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl), float(clear_min))
         _check(lib().traj_score(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), _ptr(cost),
                                 _ptr(best), _stream(stream)))
 

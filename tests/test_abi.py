@@ -31,8 +31,8 @@ def test_library_exports_every_declared_symbol():
     L = T.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert set(T.EXPORTS) | set(T.MLP_EXPORTS) | {"traj_mpc_goals", "traj_mpc_step"} == set(declared_functions())
-    for name in ("traj_mpc_goals", "traj_mpc_step"):
+    assert set(T.EXPORTS) | set(T.MLP_EXPORTS) | {"traj_mpc_goals", "traj_mpc_step", "traj_mpc_shift"} == set(declared_functions())
+    for name in ("traj_mpc_goals", "traj_mpc_step", "traj_mpc_shift"):
         assert hasattr(L, name)
 
 

@@ -71,3 +71,44 @@ def test_controls_reject_a_short_stride(T):
                                2.5, 50, T._ptr(out), T._ptr(out), T._ptr(out), T._stream(None))
     assert rc == -1
     solver.close()
+
+
+def test_collision_post_check_in_the_ranking_matches_the_oracle(T):
+    """traj_score with clear_min: goals whose trajectory comes closer than
+    clear_min to an obstacle are discarded. After a few iterations many
+    trajectories still cross obstacles, so both outcomes occur."""
+    import torch
+    batch = ragged_batch()
+    solver = T.Solver(PARAMS, batch.shapes())
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, 8)
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    n_cut = n_kept = 0
+    for clear_min in (1.0, 1.2):
+        solver.score(db, st, v_ref, cost, best, clear_min=clear_min)
+        torch.cuda.synchronize()
+        c = st.c.cpu().numpy().astype(np.float64)
+        cg, bg = cost.cpu().numpy(), best.cpu().numpy()
+        off = batch.goal_off()
+        for s, sc in enumerate(batch.scenes):
+            prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+            sl = slice(off[s], off[s + 1])
+            ref = O.meta_cost(prob, c[0][:, sl], c[1][:, sl], c[2][:, sl], 0, v_ref=float(sc.ego[2]),
+                              obs=sc.obs, clear_min=clear_min)
+            clear = np.array([O.controls(prob, sc.obs, c[0][:, g], c[1][:, g], c[2][:, g], 1.0, 1.0)[2]
+                              for g in range(off[s], off[s + 1])])
+            # the decision is compared where FP32 cannot flip it
+            sure = np.abs(clear - clear_min) > 1e-4 * clear_min
+            assert np.array_equal(np.isinf(cg[sl])[sure], np.isinf(ref)[sure]), s
+            fin = np.isfinite(ref) & np.isfinite(cg[sl])
+            assert np.allclose(cg[sl][fin], ref[fin], rtol=2e-4, atol=1e-3), s
+            if sure.all():
+                assert bg[s] == O.best_goal(ref), s
+            n_cut += int(np.sum(np.isinf(ref) & sure))
+            n_kept += int(np.sum(np.isfinite(ref) & sure))
+    print(f"post-check: {n_cut} goals discarded, {n_kept} kept")
+    assert n_cut > 0 and n_kept > 0
+    solver.close()

@@ -74,3 +74,50 @@ def test_batched_closed_loop_run(M):
     assert np.all(np.isfinite(cl.db.ego.cpu().numpy())) and np.all(np.isfinite(cl.db.obs.cpu().numpy()))
     assert m["mean_speed"] > 5.0
     assert 0 < m["mean_iterations_per_cycle"] <= 100
+
+
+def test_shift_matches_the_oracle(M):
+    """traj_mpc_shift (every goal's solution advanced by one period, the frame
+    moved back by the ego's advance) against the oracle's collocation form."""
+    import torch
+    cl = M.ClosedLoop(range(3), iters=5)
+    rng = np.random.default_rng(11)
+    G = cl.batch.n_goals
+    c = rng.normal(size=(3, 11, G)) * np.array([80.0, 4.0, 0.1])[:, None, None]
+    lam = rng.normal(size=(3, 11, G))
+    cl.st.c.copy_(torch.tensor(c, dtype=torch.float32).reshape(cl.st.c.shape))
+    cl.st.lam.copy_(torch.tensor(lam, dtype=torch.float32).reshape(cl.st.lam.shape))
+    dx = np.array([1.3, 0.0, 2.1])
+    cl.shift.copy_(torch.tensor(dx, dtype=torch.float32))
+    c = cl.st.c.cpu().numpy().astype(np.float64).reshape(3, 11, G)
+    lam = cl.st.lam.cpu().numpy().astype(np.float64).reshape(3, 11, G)
+    cl.shift_state()
+    torch.cuda.synchronize()
+    c1 = cl.st.c.cpu().numpy().astype(np.float64).reshape(3, 11, G)
+    l1 = cl.st.lam.cpu().numpy().astype(np.float64).reshape(3, 11, G)
+    off = cl.batch.goal_off()
+    u0 = 1.0 / (cl.shape[0] - 1)
+    Smat = np.abs(O.shift_matrix(11, u0))
+    Sinv = np.abs(O.shift_matrix(11, -u0))
+    for s in range(3):
+        sl = slice(off[s], off[s + 1])
+        rc, rl = O.shift_solution(c[:, :, sl], lam[:, :, sl], u0, dx[s])
+        # FP32 products of FP32-rounded entries: a few ulp of the absolute sums
+        bc = 4e-7 * (np.einsum("ik,akg->aig", Smat, np.abs(c[:, :, sl])) + np.array([dx[s], 0, 0])[:, None, None])
+        bl = 4e-7 * np.einsum("ki,akg->aig", Sinv, np.abs(lam[:, :, sl]))
+        assert np.all(np.abs(c1[:, :, sl] - rc) <= bc + 1e-30), s
+        assert np.all(np.abs(l1[:, :, sl] - rl) <= bl + 1e-30), s
+
+
+@pytest.mark.parametrize("warm", ["previous", "shifted"])
+def test_closed_loop_warm_starts_run(M, warm):
+    import torch
+    cl = M.ClosedLoop(range(64), iters=100, warm=warm, clear_min=1.0)
+    for _ in range(20):
+        cl.cycle()
+    torch.cuda.synchronize()
+    m = cl.metrics(20)
+    print(warm, m)
+    assert np.all(np.isfinite(cl.db.ego.cpu().numpy()))
+    assert m["mean_speed"] > 5.0
+    assert 0 < m["mean_iterations_per_cycle"] <= 100

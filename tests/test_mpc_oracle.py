@@ -49,3 +49,72 @@ def test_goals_and_ego_advance():
     t1 = prob.t[1]
     e = O.ego_advance(prob, c_x, np.zeros(11), np.zeros(11))
     assert np.allclose(e, [v * t1 + 0.5 * a * t1 ** 2, 0, v + a * t1, 0, a, 0, 0, 0], atol=1e-12)
+
+
+def test_shift_closed_forms():
+    """The warm start of the next cycle (the solution advanced by one period) on
+    polynomials whose shifted Bernstein coefficients are known in closed form."""
+    k = np.arange(11)
+    u0 = 1.0 / 99.0
+    # no shift: identity
+    c = np.random.default_rng(0).normal(size=(3, 11, 5))
+    lam = np.random.default_rng(1).normal(size=(3, 11, 5))
+    c1, l1 = O.shift_solution(c, lam, 0.0, 0.0)
+    assert np.allclose(c1, c, atol=1e-12) and np.allclose(l1, lam, atol=1e-12)
+    # a line x = x0 + L tau has coefficients x0 + L k/10 (linear precision);
+    # advanced by u0 and moved back by dx: x0 + L u0 - dx + L k/10
+    x0, L, dx = 2.0, 150.0, 1.7
+    c = np.zeros((3, 11, 1))
+    c[0, :, 0] = x0 + L * k / 10
+    c1, _ = O.shift_solution(c, np.zeros_like(c), u0, dx)
+    assert np.allclose(c1[0, :, 0], x0 + L * u0 - dx + L * k / 10, atol=1e-11)
+    assert np.allclose(c1[1:], 0.0, atol=1e-12)
+    # y = tau^2 has coefficients k(k-1)/90; (u + u0)^2 = u^2 + 2 u0 u + u0^2
+    c = np.zeros((3, 11, 1))
+    c[1, :, 0] = k * (k - 1) / 90.0
+    c1, _ = O.shift_solution(c, np.zeros_like(c), u0, 0.0)
+    assert np.allclose(c1[1, :, 0], k * (k - 1) / 90.0 + 2 * u0 * k / 10 + u0 ** 2, atol=1e-12)
+
+
+def test_shift_keeps_the_trajectory_and_the_multiplier_pairing():
+    rng = np.random.default_rng(5)
+    c = rng.normal(size=(3, 11, 4)) * 10
+    lam = rng.normal(size=(3, 11, 4))
+    u0, dx = 0.05, 0.8
+    c1, l1 = O.shift_solution(c, lam, u0, dx)
+    # evaluated by de Casteljau's algorithm (also valid outside [0, 1]): the new
+    # polynomial at u is the old one at u0 + u, less dx for x
+    def casteljau(coef, u):
+        b = list(coef)
+        while len(b) > 1:
+            b = [(1 - u) * b[i] + u * b[i + 1] for i in range(len(b) - 1)]
+        return b[0]
+    for u in (0.0, 0.3, 0.99, 1.0):
+        for g in range(4):
+            for a in range(3):
+                want = casteljau(c[a, :, g], u0 + u) - (dx if a == 0 else 0.0)
+                assert abs(casteljau(c1[a, :, g], u) - want) < 1e-9
+    # <lambda', c' + dx> = <lambda, c> (eq. 10's pairing), per axis and goal
+    for a in range(3):
+        back = c1[a] + (dx if a == 0 else 0.0)
+        assert np.allclose(np.sum(l1[a] * back, axis=0), np.sum(lam[a] * c[a], axis=0), atol=1e-9)
+    # advancing by u0 and then by -u0 returns the start
+    c2, l2 = O.shift_solution(c1, l1, -u0, -dx)
+    assert np.allclose(c2, c, atol=1e-9) and np.allclose(l2, lam, atol=1e-9)
+
+
+def test_traffic_scenes_keep_headways():
+    """The closed-loop starts: in every lane, each follower has at least the
+    standstill gap, a 1.5 s headway and room to shed its closing speed at 3 m/s^2."""
+    for seed in range(200):
+        sc = S.make_traffic_scene(seed)
+        veh = [(0.0, 0.0, float(sc.ego[2]))] + [(float(o[0]), float(o[1]), float(o[2])) for o in sc.obs]
+        assert len(veh) == 11
+        for i in range(len(veh)):
+            for j in range(len(veh)):
+                (xr, yr, vr), (xf, yf, vf) = veh[i], veh[j]
+                if i == j or abs(yr - yf) >= S.LANE_WIDTH / 2 or xr > xf:
+                    continue
+                need = 2.0 + 1.5 * vr + max(0.0, vr - vf) ** 2 / 6.0
+                assert xf - xr - 4.5 >= need - 1e-4, (seed, i, j)
+        assert sc.goals.shape == (256, 2)
