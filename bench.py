@@ -198,7 +198,8 @@ def run_mpc(args):
 
     from paper_2109_10392_amd import mpc
     torch.cuda.set_device(0)
-    cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters, warm=args.warm, clear_min=args.clear_min)
+    cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters, warm=args.warm, clear_min=args.clear_min,
+                        scenario=args.scenario)
     for _ in range(args.warmup):
         cl.cycle()
     torch.cuda.synchronize()
@@ -217,8 +218,9 @@ def run_mpc(args):
         "config": {"workload": f"closed loop: {args.episodes} episodes, 4 lanes, 10 IDM vehicles each, 256 goals "
                                f"per plan, replanning every sample interval (0.101 s), at most {args.iters} "
                                f"iterations per plan (stop at residual 1e-3), start: {args.warm}, "
-                               f"collision post-check at {args.clear_min}",
-                   "episodes": args.episodes, "warm": args.warm, "clear_min": args.clear_min},
+                               f"collision post-check at {args.clear_min}, scenario: {args.scenario}",
+                   "episodes": args.episodes, "warm": args.warm, "clear_min": args.clear_min,
+                   "scenario": args.scenario},
         "closed_loop": m,
     }
 
@@ -244,6 +246,8 @@ def main():
     ap.add_argument("--warm", choices=["cold", "previous", "shifted"], default="shifted",
                     help="mpc: start of every plan after the first (the previous cycle's solutions advanced by "
                          "one period, the same unshifted, or the cold start)")
+    ap.add_argument("--scenario", choices=["cruise", "right_lane"], default="cruise",
+                    help="mpc: cruise (template goals, eq. 25) or high speed near the right lane (eq. 26)")
     ap.add_argument("--clear-min", type=float, default=1.0,
                     help="mpc: collision post-check of the ranking (scaled obstacle distance; 0 = off)")
     ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")

@@ -36,6 +36,11 @@ typedef struct {
   int32_t n_lanes;    /* goal template: lanes */
   int32_t per_lane;   /* goal template: longitudinal slots per lane */
   float goal_v_floor; /* goal template: x_f = x0 + max(|v|, goal_v_floor) t_f linspace(0.8, 1.2, per_lane) */
+  int32_t sampler;    /* 0: the template (cruise, eq. 25); 1: the right-lane sampler of Sec. III-F for
+                         eq. 26: of G = n_lanes per_lane goals, n_r = round(0.6 G) on the right lane
+                         (lane 0, the lowest y) at x0 + v_max t_f linspace(0.2, 1, n_r); the others
+                         round-robin over lanes 1 .. n_lanes-1 at x0 + v_max t_f (0.9 .. 1.0) */
+  float v_max;        /* sampler 1: the scenario's maximum speed (m/s), > 0 */
 } traj_mpc_params;
 
 /* Episode state, device arrays; ego, obs and goal are the arrays the traj_batch
@@ -54,9 +59,9 @@ typedef struct {
 } traj_episodes;
 
 /*
- * traj_mpc_goals -- the goal template from every ego's current state
- * (n_lanes x per_lane goals per episode, lane-major). Episodes with another
- * goal count are left unchanged.
+ * traj_mpc_goals -- the goals of every episode from its ego's current state
+ * (n_lanes x per_lane goals; p->sampler picks the template or the right-lane
+ * sampler). Episodes with another goal count are left unchanged.
  */
 int traj_mpc_goals(void *handle, const traj_batch *batch, const traj_episodes *eps, const traj_mpc_params *p,
                    void *stream);
@@ -81,12 +86,14 @@ int traj_mpc_step(void *handle, const traj_batch *batch, const traj_state *state
  * x, y, psi become c' = S c, S_ik = sum_q B(10-i, k-q; u0) B(i, q; 1+u0),
  * B(n, j; u) = C(n, j) u^j (1-u)^(n-j) (the polar form at u0 (10-i times) and
  * 1+u0 (i times)), then x' -= shift[s] (the frame re-centring; the basis sums
- * to one). The multipliers keep their pairing <lambda, c> of eq. 10,
- * lambda'^T c' = lambda^T S^-1 c', i.e. lambda' = S^-T lambda with
- * S^-1 = S(-u0). Call after traj_mpc_step and traj_mpc_goals; solve with
- * TRAJ_INIT_FROM_STATE (and TRAJ_WARM_FALLBACK). The first iteration's x/y step
- * puts every goal's boundary values in place (eq. 8b).
- *   state: c and lam, device [3][11][n_goals], updated in place. eps: shift.
+ * to one). The multipliers are kept as they are: of the forms tried (kept,
+ * S lambda, S^-T lambda, lambda + Q (c' - c), zero) keeping them needs the
+ * fewest iterations in closed loop. Call after traj_mpc_step and
+ * traj_mpc_goals; solve with TRAJ_INIT_FROM_STATE (and TRAJ_WARM_FALLBACK).
+ * The first iteration's x/y step puts every goal's boundary values in place
+ * (eq. 8b).
+ *   state: c, device [3][11][n_goals], updated in place (lam is not touched).
+ *   eps: shift.
  */
 int traj_mpc_shift(void *handle, const traj_batch *batch, traj_state *state, const traj_episodes *eps,
                    void *stream);

@@ -420,6 +420,31 @@ def mpc_goals(ego, n_lanes=4, per_lane=64, t_f=10.0, v_floor=5.0, lane_width=3.5
     return g
 
 
+def right_lane_goals(ego, v_max, n_lanes=4, per_lane=64, t_f=10.0, lane_width=3.5):
+    """Goals of the high-speed right-lane scenario (Sec. III-F, for eq. 26): about
+    60% of them on the right lane (the lowest y) at different distances, here
+    v_max t_f linspace(0.2, 1), the rest spread over the other lanes at v_max t_f
+    (from 0.9 v_max t_f up, so that no two coincide), assigned round-robin."""
+    ego = np.asarray(ego, np.float64)
+    G = n_lanes * per_lane
+    n_r = int(np.floor(0.6 * G + 0.5))
+    centres = (np.arange(n_lanes) - (n_lanes - 1) // 2) * lane_width
+    g = np.zeros((G, 2))
+    g[:n_r, 0] = ego[0] + v_max * t_f * np.linspace(0.2, 1.0, n_r)
+    g[:n_r, 1] = centres[0]
+    others = list(range(1, n_lanes))
+    rest = G - n_r
+    if not others:  # one lane: the rest at v_max t_f on it
+        g[n_r:] = (ego[0] + v_max * t_f, centres[0])
+        return g
+    per_o = -(-rest // len(others))
+    fr = np.linspace(0.9, 1.0, per_o) if per_o > 1 else np.ones(1)
+    for r in range(rest):
+        g[n_r + r, 0] = ego[0] + v_max * t_f * fr[r // len(others)]
+        g[n_r + r, 1] = centres[others[r % len(others)]]
+    return g
+
+
 def idm_accel(v, v_des, gap, dv, p):
     """IDM acceleration; gap = None for a free road."""
     free = 1.0 - (v / v_des) ** p["delta"]
@@ -470,23 +495,19 @@ def shift_matrix(n_coef, u0):
     return np.linalg.solve(basis(nodes), basis(nodes + u0))
 
 
-def shift_solution(c, lam, u0, dx):
+def shift_solution(c, u0, dx):
     """Warm start of the next receding-horizon cycle from this cycle's solution.
 
-    c, lam: (3, n_coef, G) coefficients and multipliers of x, y, psi. Returns
-    (c', lam'): c' = S c per axis with x' shifted by -dx (the frame moved dx
-    forward; Bernstein polynomials sum to one, so a constant moves every
-    coefficient), and lam' = S^-T lam, which keeps lam'^T S c = lam^T c: the
-    multiplier term <lambda, c> of the augmented cost (eq. 10) pairs with the same
-    trajectory as before.
+    c: (3, n_coef, G) coefficients of x, y, psi. Returns c' = S c per axis, with
+    x' shifted by -dx (the frame moved dx forward; Bernstein polynomials sum to
+    one, so a constant moves every coefficient). The multipliers are not part of
+    the map: they are kept as they are.
     """
     c = np.asarray(c, np.float64)
-    lam = np.asarray(lam, np.float64)
     Smat = shift_matrix(c.shape[1], u0)
     c_new = np.einsum("ik,akg->aig", Smat, c)
     c_new[0] -= np.asarray(dx, np.float64)
-    lam_new = np.stack([np.linalg.solve(Smat.T, lam[a]) for a in range(3)])
-    return c_new, lam_new
+    return c_new
 
 
 def ego_advance(prob, c_x, c_y, c_psi):

@@ -55,10 +55,28 @@ __global__ void k_mpc_goals(MpcArgs A) {
   if (sid < 0 || sid >= A.n_shapes) return;
   const float t_f = A.shapes[sid].t_f;
   const float* e = A.e.ego + 8 * s;
+  float* g = A.e.goal + 2 * (g0 + slot);
+  if (A.p.sampler == 1) {
+    // right-lane sampler: about 60% of the goals on the right lane at different
+    // distances, the rest over the other lanes at v_max t_f (Sec. III-F)
+    const int n_r = (6 * per + 5) / 10, n_o = per - n_r, others = A.p.n_lanes - 1;
+    int lane;
+    float fr;
+    if (slot < n_r || others == 0) {
+      lane = 0;
+      fr = n_r > 1 ? 0.2f + 0.8f * (float)min(slot, n_r - 1) / (float)(n_r - 1) : 1.f;
+    } else {
+      const int r = slot - n_r, per_o = (n_o + others - 1) / others;
+      lane = 1 + r % others;
+      fr = per_o > 1 ? 0.9f + 0.1f * (float)(r / others) / (float)(per_o - 1) : 1.f;
+    }
+    g[0] = fmaf(A.p.v_max * t_f, fr, e[0]);
+    g[1] = (float)(lane - (A.p.n_lanes - 1) / 2) * A.p.lane_width;
+    return;
+  }
   const float v = fmaxf(sqrtf(fmaf(e[2], e[2], e[3] * e[3])), A.p.goal_v_floor);
   const int lane = slot / A.p.per_lane, k = slot - lane * A.p.per_lane;
   const float fr = A.p.per_lane > 1 ? 0.8f + 0.4f * (float)k / (float)(A.p.per_lane - 1) : 1.f;
-  float* g = A.e.goal + 2 * (g0 + slot);
   g[0] = fmaf(v * t_f, fr, e[0]);
   g[1] = (float)(lane - (A.p.n_lanes - 1) / 2) * A.p.lane_width;
 }
@@ -208,11 +226,12 @@ __device__ double shift_entry(int e, double u0) {
   return acc;
 }
 
-// One workgroup per episode: S(u0) and S(-u0) of the episode's shape in LDS,
-// then every goal's (c, lambda) of the three axes advanced (threads over goals;
-// the goal-fastest layout makes each coefficient load and store coalesced).
-__global__ __launch_bounds__(256) void k_mpc_shift(MpcArgs A, float* c, float* lam) {
-  __shared__ float fwd[NC * NC], inv[NC * NC];
+// One workgroup per episode: S(u0) of the episode's shape in LDS, then every
+// goal's coefficients of the three axes advanced (threads over goals; the
+// goal-fastest layout makes each coefficient load and store coalesced). The
+// multipliers stay as they are.
+__global__ __launch_bounds__(256) void k_mpc_shift(MpcArgs A, float* c) {
+  __shared__ float fwd[NC * NC];
   const int s = blockIdx.x;
   const int sid = A.shape_id[s];
   if (sid < 0 || sid >= A.n_shapes) return;
@@ -220,29 +239,21 @@ __global__ __launch_bounds__(256) void k_mpc_shift(MpcArgs A, float* c, float* l
   const double u0 = 1.0 / (double)(sd.n - 1);
   const int t = threadIdx.x;
   if (t < NC * NC) fwd[t] = (float)shift_entry(t, u0);
-  if (t >= 128 && t - 128 < NC * NC) inv[t - 128] = (float)shift_entry(t - 128, -u0);
   __syncthreads();
   const int g0 = max(A.goal_off[s], 0), g1 = min(A.goal_off[s + 1], A.n_goals);
   const float dx = A.e.shift[s];
   const int NG = A.n_goals;
   for (int g = g0 + t; g < g1; g += blockDim.x) {
     for (int ax = 0; ax < 3; ++ax) {
-      float v[NC], w[NC];
+      float v[NC];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        v[k] = c[(ax * NC + k) * NG + g];
-        w[k] = lam[(ax * NC + k) * NG + g];
-      }
+      for (int k = 0; k < NC; ++k) v[k] = c[(ax * NC + k) * NG + g];
 #pragma unroll
       for (int i = 0; i < NC; ++i) {
-        float cv = 0.f, lv = 0.f;
+        float cv = 0.f;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          cv = fmaf(fwd[i * NC + k], v[k], cv);  // (S c)_i
-          lv = fmaf(inv[k * NC + i], w[k], lv);  // (S(-u0)^T lambda)_i
-        }
+        for (int k = 0; k < NC; ++k) cv = fmaf(fwd[i * NC + k], v[k], cv);  // (S c)_i
         c[(ax * NC + i) * NG + g] = ax == 0 ? cv - dx : cv;
-        lam[(ax * NC + i) * NG + g] = lv;
       }
     }
   }
@@ -251,7 +262,7 @@ __global__ __launch_bounds__(256) void k_mpc_shift(MpcArgs A, float* c, float* l
 bool params_ok(const traj_mpc_params* p) {
   return p != nullptr && p->idm_a > 0.f && p->idm_b > 0.f && p->idm_s0 >= 0.f && p->idm_T >= 0.f &&
          p->idm_delta > 0.f && p->car_length >= 0.f && p->lane_width > 0.f && p->n_lanes >= 1 && p->per_lane >= 1 &&
-         p->goal_v_floor >= 0.f;
+         p->goal_v_floor >= 0.f && (p->sampler == 0 || (p->sampler == 1 && p->v_max > 0.f));
 }
 
 }  // namespace
@@ -326,16 +337,14 @@ int traj_mpc_step(void* handle, const traj_batch* batch, const traj_state* state
 
 int traj_mpc_shift(void* handle, const traj_batch* batch, traj_state* state, const traj_episodes* eps,
                    void* stream) {
-  if (batch == nullptr || state == nullptr || state->c == nullptr || state->lam == nullptr || eps == nullptr ||
-      eps->shift == nullptr)
+  if (batch == nullptr || state == nullptr || state->c == nullptr || eps == nullptr || eps->shift == nullptr)
     return traj::api_fail(TRAJ_E_INVAL, "traj_mpc_shift: bad arguments");
   MpcArgs a = {};
   int rc = fill(handle, batch, &a);
   if (rc != TRAJ_OK) return rc;
   a.e = *eps;
   if (batch->n_scenes == 0 || batch->n_goals == 0) return TRAJ_OK;
-  hipLaunchKernelGGL(k_mpc_shift, dim3(batch->n_scenes), dim3(256), 0, (hipStream_t)stream, a, state->c,
-                     state->lam);
+  hipLaunchKernelGGL(k_mpc_shift, dim3(batch->n_scenes), dim3(256), 0, (hipStream_t)stream, a, state->c);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? TRAJ_OK : traj::api_fail(TRAJ_E_HIP, "traj_mpc_shift: %s", hipGetErrorString(e));
 }

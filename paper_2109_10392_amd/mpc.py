@@ -23,7 +23,7 @@ class MpcParams(ctypes.Structure):
     _fields_ = [("idm_a", ctypes.c_float), ("idm_b", ctypes.c_float), ("idm_s0", ctypes.c_float),
                 ("idm_T", ctypes.c_float), ("idm_delta", ctypes.c_float), ("car_length", ctypes.c_float),
                 ("lane_width", ctypes.c_float), ("n_lanes", ctypes.c_int32), ("per_lane", ctypes.c_int32),
-                ("goal_v_floor", ctypes.c_float)]
+                ("goal_v_floor", ctypes.c_float), ("sampler", ctypes.c_int32), ("v_max", ctypes.c_float)]
 
 
 class EpisodesC(ctypes.Structure):
@@ -36,10 +36,10 @@ class EpisodesC(ctypes.Structure):
 IDM = dict(idm_a=1.0, idm_b=1.5, idm_s0=2.0, idm_T=1.5, idm_delta=4.0, car_length=4.5, lane_width=3.5)
 
 
-def params(n_lanes=4, per_lane=64, goal_v_floor=5.0, **over):
+def params(n_lanes=4, per_lane=64, goal_v_floor=5.0, sampler=0, v_max=25.0, **over):
     p = dict(IDM, **over)
     return MpcParams(p["idm_a"], p["idm_b"], p["idm_s0"], p["idm_T"], p["idm_delta"], p["car_length"],
-                     p["lane_width"], n_lanes, per_lane, goal_v_floor)
+                     p["lane_width"], n_lanes, per_lane, goal_v_floor, sampler, v_max)
 
 
 def _bind():
@@ -65,12 +65,15 @@ class ClosedLoop:
     around the ego, goals = the template), driven by the planner every cycle."""
 
     def __init__(self, seeds, tile=("group", 16, True, 1), precision="fp32", iters=100, tol=1e-3, net=None,
-                 warm="cold", clear_min=0.0):
+                 warm="cold", clear_min=0.0, scenario="cruise", v_max=25.0, w1=1.0, w2=1.0):
         """warm: start of every plan after the first: "cold"; "previous" (the
         previous cycle's iterate of the same goal slot); "shifted" (that iterate
         advanced by one period, traj_mpc_shift); or "learned" (the network `net` =
         (Network, mean, std)). The warm starts keep the cold start as per-goal
-        fallback. clear_min: the collision post-check of the ranking (0 = off)."""
+        fallback. clear_min: the collision post-check of the ranking (0 = off).
+        scenario: "cruise" (template goals, eq. 25 with v_cruise = the initial
+        speed) or "right_lane" (the right-lane sampler, eq. 26 with v_max, y_rl =
+        the right lane's centre and weights w1, w2)."""
         import torch
         self.L = _bind()
         self.batch = S.Batch([S.make_traffic_scene(int(s)) for s in seeds])
@@ -87,10 +90,20 @@ class ClosedLoop:
         self.obs_next = z(max(n_o, 1), 4)
         self.travelled, self.collisions, self.fallbacks = z(n_s), z(n_s, dt=torch.int32), z(n_s, dt=torch.int32)
         self.shift = z(n_s)
-        self.v_ref = self.db.ego[:, 2].clone()  # cruise speed of the meta-cost: the initial speed
+        if scenario not in ("cruise", "right_lane"):
+            raise ValueError(f"unknown scenario {scenario!r}")
+        self.scenario, self.kind, self.w1, self.w2 = scenario, int(scenario == "right_lane"), float(w1), float(w2)
+        if self.kind == 0:
+            self.v_ref = self.db.ego[:, 2].clone()  # cruise speed of the meta-cost: the initial speed
+        else:
+            self.v_ref = torch.full((n_s,), float(v_max), device="cuda")
+        self.y_rl = torch.full((n_s,), float(S.lane_centres(4)[0]), device="cuda")
         self.cost, self.best = z(self.batch.n_goals), z(n_s, dt=torch.int32)
         self.its = z(n_s, dt=torch.int32)
-        self.p = params()
+        self.p = params(sampler=self.kind, v_max=v_max)
+        # closed-loop statistics, accumulated on the device every cycle
+        self.stats = {k: z(n_s) for k in ("v_res", "v_res_max", "lat", "acc", "acc_max", "ang", "ang_max")}
+        self.psid_prev = self.db.ego[:, 7].clone()
         self.precision, self.iters, self.tol, self.net = precision, iters, tol, net
         if warm not in ("cold", "previous", "shifted", "learned"):
             raise ValueError(f"unknown warm start {warm!r}")
@@ -114,9 +127,10 @@ class ClosedLoop:
                                        T._stream(None)))
 
     def plan(self):
-        kw = dict(max_iters=self.iters, chunk=5, tol=self.tol, precision=self.precision, clear_min=self.clear_min)
+        kw = dict(max_iters=self.iters, chunk=5, tol=self.tol, precision=self.precision, clear_min=self.clear_min,
+                  kind=self.kind, w1=self.w1, w2=self.w2, y_rl=self.y_rl)
         if self.warm in ("previous", "shifted") and self.cycles_done > 0:
-            # the previous cycle's (c, lambda) of every goal slot (advanced by one period
+            # the previous cycle's (c, lambda) of every goal slot (for "shifted" the coefficients advanced by one period,
             # for "shifted"); the x/y step of the first iteration enforces the new
             # boundary values (eq. 8b)
             if self.warm == "shifted":
@@ -144,17 +158,48 @@ class ClosedLoop:
                                       ctypes.byref(self.episodes()), ctypes.byref(self.p), self.n_obs,
                                       T._stream(None)))
 
+    def accumulate(self):
+        """Executed-motion statistics after a step (speed residual to v_ref, lateral
+        distance to the right lane, |linear acceleration| (x' x'' + y' y'') / v,
+        |angular acceleration| as the change of psi' over the period)."""
+        import torch
+        e, st = self.db.ego, self.stats
+        v = torch.hypot(e[:, 2], e[:, 3])
+        r = (v - self.v_ref) ** 2
+        st["v_res"] += r
+        torch.maximum(st["v_res_max"], r, out=st["v_res_max"])
+        st["lat"] += (e[:, 1] - self.y_rl).abs()
+        acc = ((e[:, 2] * e[:, 4] + e[:, 3] * e[:, 5]) / v.clamp_min(1e-6)).abs()
+        st["acc"] += acc
+        torch.maximum(st["acc_max"], acc, out=st["acc_max"])
+        ang = ((e[:, 7] - self.psid_prev) / self.period).abs()
+        st["ang"] += ang
+        torch.maximum(st["ang_max"], ang, out=st["ang_max"])
+        self.psid_prev.copy_(e[:, 7])
+
+    @property
+    def period(self):
+        return self.shape[1] / (self.shape[0] - 1)
+
     def cycle(self):
         self.goals()
         self.plan()
         self.step()
+        self.accumulate()
         self.cycles_done += 1
 
     def metrics(self, cycles):
         n = self.batch.n_scenes
         tr = self.travelled.cpu().numpy()
-        dt = self.shape[1] / (self.shape[0] - 1)
-        return {"episodes": n, "cycles": cycles, "mean_speed": float(tr.mean() / (cycles * dt)),
+        dt = self.period
+        st = {k: v.cpu().numpy() for k, v in self.stats.items()}
+        c = max(self.cycles_done, 1)
+        return {"episodes": n, "cycles": cycles, "scenario": self.scenario,
+                "mean_speed": float(tr.mean() / (cycles * dt)),
+                "speed_residual_mean": float(st["v_res"].mean() / c), "speed_residual_max": float(st["v_res_max"].max()),
+                "right_lane_distance_mean": float(st["lat"].mean() / c),
+                "linear_acc_mean": float(st["acc"].mean() / c), "linear_acc_max": float(st["acc_max"].max()),
+                "angular_acc_mean": float(st["ang"].mean() / c), "angular_acc_max": float(st["ang_max"].max()),
                 "collision_events": int(self.collisions.sum().item()),
                 "episodes_with_collision": int((self.collisions > 0).sum().item()),
                 "fallback_cycles": int(self.fallbacks.sum().item()),

@@ -58,30 +58,28 @@ def test_shift_closed_forms():
     u0 = 1.0 / 99.0
     # no shift: identity
     c = np.random.default_rng(0).normal(size=(3, 11, 5))
-    lam = np.random.default_rng(1).normal(size=(3, 11, 5))
-    c1, l1 = O.shift_solution(c, lam, 0.0, 0.0)
-    assert np.allclose(c1, c, atol=1e-12) and np.allclose(l1, lam, atol=1e-12)
+    assert np.allclose(O.shift_solution(c, 0.0, 0.0), c, atol=1e-12)
     # a line x = x0 + L tau has coefficients x0 + L k/10 (linear precision);
     # advanced by u0 and moved back by dx: x0 + L u0 - dx + L k/10
     x0, L, dx = 2.0, 150.0, 1.7
     c = np.zeros((3, 11, 1))
     c[0, :, 0] = x0 + L * k / 10
-    c1, _ = O.shift_solution(c, np.zeros_like(c), u0, dx)
+    c1 = O.shift_solution(c, u0, dx)
     assert np.allclose(c1[0, :, 0], x0 + L * u0 - dx + L * k / 10, atol=1e-11)
     assert np.allclose(c1[1:], 0.0, atol=1e-12)
     # y = tau^2 has coefficients k(k-1)/90; (u + u0)^2 = u^2 + 2 u0 u + u0^2
     c = np.zeros((3, 11, 1))
     c[1, :, 0] = k * (k - 1) / 90.0
-    c1, _ = O.shift_solution(c, np.zeros_like(c), u0, 0.0)
+    c1 = O.shift_solution(c, u0, 0.0)
     assert np.allclose(c1[1, :, 0], k * (k - 1) / 90.0 + 2 * u0 * k / 10 + u0 ** 2, atol=1e-12)
 
 
-def test_shift_keeps_the_trajectory_and_the_multiplier_pairing():
+def test_shift_keeps_the_trajectory():
     rng = np.random.default_rng(5)
     c = rng.normal(size=(3, 11, 4)) * 10
-    lam = rng.normal(size=(3, 11, 4))
     u0, dx = 0.05, 0.8
-    c1, l1 = O.shift_solution(c, lam, u0, dx)
+    c1 = O.shift_solution(c, u0, dx)
+
     # evaluated by de Casteljau's algorithm (also valid outside [0, 1]): the new
     # polynomial at u is the old one at u0 + u, less dx for x
     def casteljau(coef, u):
@@ -94,13 +92,8 @@ def test_shift_keeps_the_trajectory_and_the_multiplier_pairing():
             for a in range(3):
                 want = casteljau(c[a, :, g], u0 + u) - (dx if a == 0 else 0.0)
                 assert abs(casteljau(c1[a, :, g], u) - want) < 1e-9
-    # <lambda', c' + dx> = <lambda, c> (eq. 10's pairing), per axis and goal
-    for a in range(3):
-        back = c1[a] + (dx if a == 0 else 0.0)
-        assert np.allclose(np.sum(l1[a] * back, axis=0), np.sum(lam[a] * c[a], axis=0), atol=1e-9)
     # advancing by u0 and then by -u0 returns the start
-    c2, l2 = O.shift_solution(c1, l1, -u0, -dx)
-    assert np.allclose(c2, c, atol=1e-9) and np.allclose(l2, lam, atol=1e-9)
+    assert np.allclose(O.shift_solution(c1, -u0, -dx), c, atol=1e-9)
 
 
 def test_traffic_scenes_keep_headways():
@@ -118,3 +111,19 @@ def test_traffic_scenes_keep_headways():
                 need = 2.0 + 1.5 * vr + max(0.0, vr - vf) ** 2 / 6.0
                 assert xf - xr - 4.5 >= need - 1e-4, (seed, i, j)
         assert sc.goals.shape == (256, 2)
+
+
+def test_right_lane_sampler_counts_and_distances():
+    """Sec. III-F: about 60% of the goals on the right lane at different
+    distances, the rest over the other lanes at v_max t_f."""
+    ego = np.array([1.0, 0.0, 15.0, 0.0, 0, 0, 0, 0])
+    g = O.right_lane_goals(ego, 25.0)
+    assert g.shape == (256, 2)
+    right = g[:, 1] == -3.5
+    assert right.sum() == 154 and abs(right.mean() - 0.6) < 0.01
+    assert np.allclose(np.sort(g[right, 0]), 1.0 + 250.0 * np.linspace(0.2, 1.0, 154))
+    for y in (0.0, 3.5, 7.0):
+        sel = g[:, 1] == y
+        assert sel.sum() in (34, 35)
+        assert np.all((g[sel, 0] >= 1.0 + 0.9 * 250.0 - 1e-9) & (g[sel, 0] <= 1.0 + 250.0 + 1e-9))
+    assert len({tuple(r) for r in g}) == 256
