@@ -33,13 +33,13 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "d0a2adf919edca022172f33c3afbbbc946804eb57c7979c5b76e8e410009046a",
-              "bytes_per_launch": int((280.28 * 2.0 + 2272.0) * 1024),
+              "sha256": "011bf7b28039e34c098b6f05867278ebae5c174a2b0862761f573a4057061b58",
+              "bytes_per_launch": int((263.0 * 2.0 + 2272.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "30a9a560b3e01209fe1b4c57de22931237dea86004490fbf55bd8fac9671f682",
-               "bytes_per_launch": int((84581.9 * 2.0 + 278059.4) * 1024),
+               "sha256": "0ac32428f345b367e19f280085a47a5bcd92f6b88b2d819a9d3f262fdf3ff9cd",
+               "bytes_per_launch": int((79314.8 * 2.0 + 277566.7) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
