@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtraj.so")
 
-SOURCES = ["traj_setup.hip", "traj_solve.hip", "traj_mfma.hip", "traj_group.hip", "traj_score.hip", "traj_mlp.hip", "traj_mpc.hip", "traj_api.hip"]
+SOURCES = ["traj_setup.hip", "traj_solve.hip", "traj_mfma.hip", "traj_group.hip", "traj_score.hip", "traj_mlp.hip", "traj_mpc.hip", "traj_frenet.hip", "traj_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -469,4 +469,12 @@ int handle_view(void* handle, const ShapeDesc** shapes, const float** tables, in
   *ell_b = h->p.b;
   return TRAJ_OK;
 }
+
+// the longest n_time of the handle's shapes (host copy, no device access)
+int handle_max_n(void* handle, int* max_n) {
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  *max_n = h->max_n;
+  return TRAJ_OK;
+}
 }  // namespace traj

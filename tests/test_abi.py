@@ -3,6 +3,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2109_10392_amd import scenes as S
@@ -31,8 +32,10 @@ def test_library_exports_every_declared_symbol():
     L = T.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert set(T.EXPORTS) | set(T.MLP_EXPORTS) | {"traj_mpc_goals", "traj_mpc_step", "traj_mpc_shift"} == set(declared_functions())
-    for name in ("traj_mpc_goals", "traj_mpc_step", "traj_mpc_shift"):
+    extra = {"traj_mpc_goals", "traj_mpc_step", "traj_mpc_shift", "traj_road_from_global", "traj_road_to_global",
+             "traj_trajectory_to_global"}
+    assert set(T.EXPORTS) | set(T.MLP_EXPORTS) | extra == set(declared_functions())
+    for name in sorted(extra):
         assert hasattr(L, name)
 
 
@@ -95,3 +98,17 @@ def test_mlp_dimensions_are_validated_on_the_host():
     for bad in (T.MlpDims(63, 256, 3, 16896), T.MlpDims(64, 256, 0, 16896), T.MlpDims(64, 256, 9, 16896)):
         assert L.traj_mlp_param_count(ctypes.byref(bad), ctypes.byref(n)) == -1
     assert L.traj_gemm_bf16(0, 0, 12, 16, 16, None, None, None, 0, None, None) == -1
+
+
+def test_road_is_validated_on_the_host():
+    """Bad centre-lines are rejected before anything is launched."""
+    from paper_2109_10392_amd import frenet as F
+    L = F._bind()
+    for segs in ([], [(0.0, 0.0)], [(10.0, 1.0)], [(float("nan"), 0.0)], [(1.0, 0.0)] * 65):
+        r = F.Road(segs if segs else np.zeros((0, 2)))
+        rc = L.traj_road_to_global(ctypes.byref(r.c_struct()), 1, None, None, None)
+        assert rc == -1 and L.traj_last_error()
+    good = F.Road([(10.0, 0.1)])  # turns by 1 rad
+    assert L.traj_road_from_global(ctypes.byref(good.c_struct()), 2, 1, None, None, None) == -1
+    assert L.traj_road_from_global(ctypes.byref(good.c_struct()), 0, 0, None, None, None) == 0
+    assert L.traj_road_to_global(ctypes.byref(good.c_struct()), 0, None, None, None) == 0

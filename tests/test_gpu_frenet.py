@@ -1,0 +1,152 @@
+"""Road-attached frame on the GPU against the FP64 oracle (which defines the
+frame by quadrature and root finding, not by the arc formulas the device uses):
+global -> road frame for obstacles and ego states, road -> global for points,
+and a trajectory planned in the road frame of a curved road mapped back."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import traj_oracle as O
+from oracle.frenet_oracle import RoadOracle
+from paper_2109_10392_amd import scenes as S
+from tests.test_gpu_parity import PARAMS
+
+pytestmark = pytest.mark.gpu
+
+SEGS = [(50.0, 0.0), (100.0, 1 / 80.0), (30.0, 0.0), (80.0, -1 / 60.0), (40.0, 0.0)]
+START = (10.0, 20.0, -0.2)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_10392_amd import frenet
+    return frenet
+
+
+def _points(R, n, rng, margin=1.5):
+    """Road-frame draws away from the joints (where the curvature jumps), mapped to
+    global FP32 positions; returns the FP32 globals."""
+    joints = R.S
+    out = []
+    while len(out) < n:
+        s, d = rng.uniform(-15, R.length + 15), rng.uniform(-8, 8)
+        if np.min(np.abs(joints - s)) < margin:
+            continue
+        out.append(R.to_global(s, d)[:2])
+    return np.array(out, np.float32)
+
+
+def test_from_global_matches_the_oracle(F):
+    import torch
+    R = RoadOracle(SEGS, *START)
+    road = F.Road(SEGS, *START)
+    rng = np.random.default_rng(7)
+    xy = _points(R, 40, rng)
+    obs = np.concatenate([xy, rng.uniform(-15, 15, (40, 2)).astype(np.float32)], 1)
+    ego = np.concatenate([xy, rng.uniform(-15, 15, (40, 2)), rng.uniform(-2, 2, (40, 2)),
+                          rng.uniform(-0.5, 0.5, (40, 1)), rng.uniform(-0.2, 0.2, (40, 1))], 1).astype(np.float32)
+    go = road.from_global(torch.tensor(obs, device="cuda"), out=torch.empty(40, 4, device="cuda"))
+    ge = road.from_global(torch.tensor(ego, device="cuda"), out=torch.empty(40, 8, device="cuda"))
+    go, ge = go.cpu().numpy().astype(np.float64), ge.cpu().numpy().astype(np.float64)
+    for i in range(40):
+        ro = R.from_global(obs[i].astype(np.float64))
+        re = R.from_global(ego[i].astype(np.float64))
+        # FP32 outputs of FP64 arithmetic on the same FP32 inputs
+        assert abs(go[i, 0] - ro[0]) <= 2e-5 * max(1.0, abs(ro[0])) and abs(go[i, 1] - ro[1]) <= 2e-5, (i, go[i], ro)
+        assert np.allclose(go[i, 2:], ro[2:], rtol=1e-5, atol=1e-5), (i, go[i], ro)
+        assert np.allclose(ge[i, :4], re[:4], rtol=2e-5, atol=2e-5), (i, ge[i], re)
+        assert np.allclose(ge[i, 4:6], re[4:6], rtol=1e-4, atol=1e-4), (i, ge[i], re)
+        assert np.allclose(ge[i, 6:], re[6:], rtol=1e-5, atol=1e-5), (i, ge[i], re)
+
+
+def test_to_global_and_round_trip(F):
+    import torch
+    R = RoadOracle(SEGS, *START)
+    road = F.Road(SEGS, *START)
+    rng = np.random.default_rng(8)
+    sd = np.stack([rng.uniform(-30, R.length + 30, 200), rng.uniform(-9, 9, 200)], 1).astype(np.float32)
+    sd[:5, 0] = [0.0, 50.0, 150.0, 180.0, R.length]  # the joints and the ends
+    g = road.to_global(torch.tensor(sd, device="cuda"))
+    back = road.from_global(torch.cat([g[:, :2], torch.zeros(200, 2, device="cuda")], 1),
+                            out=torch.empty(200, 4, device="cuda"))
+    g, back = g.cpu().numpy(), back.cpu().numpy()
+    for i in range(200):
+        ref = R.to_global(float(sd[i, 0]), float(sd[i, 1]))
+        assert np.allclose(g[i, :2], ref[:2], rtol=0, atol=2e-5 * max(1.0, np.abs(ref[:2]).max())), (i, g[i], ref)
+        assert abs(g[i, 2] - ref[2]) < 1e-6
+        assert abs(back[i, 0] - sd[i, 0]) < 1e-4 * max(1.0, abs(sd[i, 0])) and abs(back[i, 1] - sd[i, 1]) < 1e-4
+    # nothing to do
+    assert road.to_global(torch.zeros(0, 2, device="cuda")).shape == (0, 3)
+
+
+def _bern(c, t, t_f, der=0):
+    n = len(c) - 1
+    tau = t / t_f
+    if der == 0:
+        return sum(c[k] * math.comb(n, k) * tau ** k * (1 - tau) ** (n - k) for k in range(n + 1))
+    raise ValueError
+
+
+def test_plan_on_a_curved_road_and_map_back(F):
+    """A scene on a 200 m radius left bend: ego and traffic converted to the road
+    frame on the device, planned there with the straight-road solver, the chosen
+    trajectory mapped back to the global frame and checked against the oracle."""
+    import torch
+    from paper_2109_10392_amd import traj as T
+    segs = [(20.0, 0.0), (500.0, 1 / 200.0)]
+    R = RoadOracle(segs, 0.0, 0.0, 0.0)
+    road = F.Road(segs)
+    sc = S.make_template_scene(3)
+    # global states: along-road draws of the template scene placed on the bend
+    ego_g = np.zeros((1, 8), np.float32)
+    p = R.to_global(25.0, 0.0)  # on the arc (not at its joint with the straight)
+    v0 = float(sc.ego[2])
+    ego_g[0, :2] = p[:2]
+    ego_g[0, 2:4] = v0 * math.cos(p[2]), v0 * math.sin(p[2])
+    ego_g[0, 6] = p[2]
+    ego_g[0, 7] = v0 / 200.0
+    ego_g[0, 4:6] = -math.sin(p[2]) * v0 * v0 / 200.0, math.cos(p[2]) * v0 * v0 / 200.0
+    obs_g = np.zeros((sc.obs.shape[0], 4), np.float32)
+    for j, o in enumerate(sc.obs):
+        q = R.to_global(25.0 + float(o[0]), float(o[1]))
+        r = 200.0 - float(o[1])  # radius of its lane
+        obs_g[j, :2] = q[:2]
+        obs_g[j, 2:] = float(o[2]) * r / 200.0 * math.cos(q[2]), float(o[2]) * r / 200.0 * math.sin(q[2])
+    e = road.from_global(torch.tensor(ego_g, device="cuda"), out=torch.empty(1, 8, device="cuda")).cpu().numpy()
+    ob = road.from_global(torch.tensor(obs_g, device="cuda"), out=torch.empty(len(obs_g), 4, device="cuda"))
+    ob = ob.cpu().numpy()
+    # the bend is straight in the road frame: lane offsets and along-road speeds come back
+    assert abs(e[0, 1]) < 1e-3 and abs(e[0, 2] - v0) < 1e-3 and abs(e[0, 3]) < 1e-3
+    assert np.allclose(ob[:, 1], sc.obs[:, 1], atol=1e-3) and np.allclose(ob[:, 2], sc.obs[:, 2], atol=1e-3)
+    # plan in the road frame (s measured from the ego)
+    rs = S.Scene(ego=e[0].copy(), obs=ob.copy(), goals=sc.goals.copy(), n_time=100, t_f=10.0, n_lanes=4, seed=3)
+    s0 = float(rs.ego[0])
+    rs.ego[0] = 0.0
+    rs.obs[:, 0] -= s0
+    batch = S.Batch([rs])
+    solver = T.Solver(PARAMS, batch.shapes())
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, 60)
+    v_ref = torch.tensor([v0], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(1, device="cuda", dtype=torch.int32)
+    solver.score(db, st, v_ref, cost, best)
+    # map back: the road frame of the solve starts at the ego (s0), so shift the road's start
+    road_s = F.Road(segs, 0.0, 0.0, 0.0)
+    c = st.c.cpu().numpy().astype(np.float64)
+    cx = c[0, :, int(best.item())].copy()
+    cx += s0  # back to arc length from the road's start (the basis sums to one)
+    st.c[0, :, int(best.item())] += s0
+    out = road_s.trajectory(solver, db, st, best, stride=100).cpu().numpy()[0]
+    cy = c[1, :, int(best.item())]
+    ts = np.linspace(0, 10.0, 100)
+    ref = R.trajectory_to_global(lambda t: _bern(cx, t, 10.0), lambda t: _bern(cy, t, 10.0), ts[1:-1])
+    assert np.allclose(out[1:-1, :2], ref[:, :2], rtol=0, atol=2e-3), np.abs(out[1:-1, :2] - ref[:, :2]).max()
+    dh = np.angle(np.exp(1j * (out[1:-1, 2] - ref[:, 2])))
+    assert np.max(np.abs(dh)) < 1e-4, np.max(np.abs(dh))
+    solver.close()
