@@ -250,8 +250,8 @@ def main():
                     help="mpc: cruise (template goals, eq. 25) or high speed near the right lane (eq. 26)")
     ap.add_argument("--clear-min", type=float, default=1.0,
                     help="mpc: collision post-check of the ranking (scaled obstacle distance; 0 = off)")
-    ap.add_argument("--train-scenes", type=int, default=20000, help="warmstart: solved scenes to train on")
-    ap.add_argument("--test-scenes", type=int, default=2048, help="warmstart: held-out scenes timed")
+    ap.add_argument("--train-scenes", type=int, default=100000, help="warmstart: solved scenes to train on")
+    ap.add_argument("--test-scenes", type=int, default=10000, help="warmstart: held-out scenes timed")
     ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
