@@ -10,18 +10,6 @@ namespace {
 
 constexpr int SCORE_THREADS = WAVE * GOALS_PER_WG;
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
-  return v;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int d = WAVE / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, WAVE));
-  return v;
-}
-
 // scene of a goal: largest s with goal_off[s] <= g
 __device__ int scene_of(const int32_t* goal_off, int n_scenes, int g) {
   int lo = 0, hi = n_scenes - 1;
@@ -35,15 +23,46 @@ __device__ int scene_of(const int32_t* goal_off, int n_scenes, int g) {
   return lo;
 }
 
-// One wave per goal, lanes over time samples.
-__global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int g = blockIdx.x * GOALS_PER_WG + (threadIdx.x >> 6);
-  if (g >= A.n_goals) return;
+// Sixteen lanes per goal (a DPP row), four goals per wavefront: lane r of a
+// goal's row takes the samples r, r + 16, ...; the row's partial sums, maxima and
+// minima are combined by four DPP steps. Coefficients are read once per lane
+// (the goal-fastest layout keeps them coalesced); the basis rows and obstacles
+// are shared by the goals of a scene.
+constexpr int COST_LANES = 16;
+constexpr int COST_THREADS = 256;
+constexpr int COST_GOALS = COST_THREADS / COST_LANES;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // p <-> 7 - p within 8 lanes
+constexpr int DPP_MIRROR = 0x140;       // p <-> 15 - p within 16 lanes
+
+// combined over the 16 lanes of a row, result in every lane of the row
+__device__ __forceinline__ float row_sum(float v) {
+  v += dpp_row<DPP_XOR1>(v);
+  v += dpp_row<DPP_XOR2>(v);
+  v += dpp_row<DPP_HALF_MIRROR>(v);
+  return v + dpp_row<DPP_MIRROR>(v);
+}
+__device__ __forceinline__ float row_max(float v) {
+  v = fmaxf(v, dpp_row<DPP_XOR1>(v));
+  v = fmaxf(v, dpp_row<DPP_XOR2>(v));
+  v = fmaxf(v, dpp_row<DPP_HALF_MIRROR>(v));
+  return fmaxf(v, dpp_row<DPP_MIRROR>(v));
+}
+
+__global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
+  const int r = threadIdx.x & (COST_LANES - 1);
+  const int g = blockIdx.x * COST_GOALS + (int)(threadIdx.x / COST_LANES);
+  if (g >= A.n_goals) return;  // whole rows leave together
   const int s = scene_of(A.goal_off, A.n_scenes, g);
   const int sid = A.shape_id[s];
   if (sid < 0 || sid >= A.n_shapes) {
-    if (lane == 0) A.cost[g] = __builtin_nanf("");
+    if (r == 0) A.cost[g] = __builtin_nanf("");
     return;
   }
   const ShapeDesc sd = A.shapes[sid];
@@ -61,13 +80,16 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
   const bool check = A.clear_min > 0.f;
   const int o0 = check ? A.obs_off[s] : 0, m = check ? A.obs_off[s + 1] - o0 : 0;
   const float dt = sd.t_f / (float)(n - 1);
+  const float ia = 1.f / A.a, ib = 1.f / A.b;
+  const float* P0 = T + tab_basis(n, 0);
+  const float* P1 = T + tab_basis(n, 1);
   float acc = 0.f, pmax = 0.f, clear = __builtin_inff();
-  for (int t = lane; t < n; t += WAVE) {
+  for (int t = r; t < n; t += COST_LANES) {
     float xd = 0.f, yd = 0.f, x = 0.f, y = 0.f, psi = 0.f;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const float p = T[tab_basis(n, 0) + k * n + t];
-      const float pd = T[tab_basis(n, 1) + k * n + t];
+      const float p = P0[k * n + t];
+      const float pd = P1[k * n + t];
       xd = fmaf(pd, cx[k], xd);
       yd = fmaf(pd, cy[k], yd);
       x = fmaf(p, cx[k], x);
@@ -77,8 +99,8 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
     // squared scaled distance to every obstacle's constant-velocity prediction (eq. 1e)
     const float tm = (float)t * dt;
     for (int j = 0; j < m; ++j) {
-      const float* o = A.obs + 4 * (o0 + j);
-      const float dx = (x - fmaf(o[2], tm, o[0])) / A.a, dy = (y - fmaf(o[3], tm, o[1])) / A.b;
+      const float4 o = reinterpret_cast<const float4*>(A.obs)[o0 + j];
+      const float dx = (x - fmaf(o.z, tm, o.x)) * ia, dy = (y - fmaf(o.w, tm, o.y)) * ib;
       clear = fminf(clear, fmaf(dx, dx, dy * dy));
     }
     const float v = sqrtf(fmaf(xd, xd, yd * yd));
@@ -91,12 +113,11 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_cost(ScoreArgs A) {
     }
     pmax = fmaxf(pmax, fabsf(psi));
   }
-  acc = wave_sum(acc);
-  pmax = wave_max(pmax);
-#pragma unroll
-  for (int d = WAVE / 2; d > 0; d >>= 1) clear = fminf(clear, __shfl_xor(clear, d, WAVE));
+  acc = row_sum(acc);
+  pmax = row_max(pmax);
+  clear = -row_max(-clear);
   const bool hit = check && !(sqrtf(clear) >= A.clear_min);
-  if (lane == 0) A.cost[g] = (pmax > A.psi_max || hit) ? __builtin_inff() : acc;
+  if (r == 0) A.cost[g] = (pmax > A.psi_max || hit) ? __builtin_inff() : acc;
 }
 
 // One workgroup per scene: lowest index attaining the minimum finite cost.
@@ -254,8 +275,8 @@ hipError_t launch_converge_check(const int32_t* goal_off, const float* resid, co
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream) {
   (void)max_n;
   if (a.n_goals > 0) {
-    const int blocks = (a.n_goals + GOALS_PER_WG - 1) / GOALS_PER_WG;
-    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(SCORE_THREADS), 0, stream, a);
+    const int blocks = (a.n_goals + COST_GOALS - 1) / COST_GOALS;
+    hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(COST_THREADS), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
