@@ -218,3 +218,55 @@ def test_bf16x3_group_precision_report(T):
     with open(os.path.join("gpurun_out", "bf16x3_group_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9
+
+
+def test_uneven_full_batch_sampled(T):
+    """The uneven workload at its full size (512 scenes, 118,830 goals, T in {50,
+    100, 150}, 4-64 obstacles) in the launch configuration its benchmark times
+    (group kernel, 16 goals, persistent, FP32, 100 iterations): the first, middle
+    and last goal of twelve scenes spanning the shapes against the oracle, and the
+    ranking of those scenes against the oracle's meta-cost of the same
+    coefficients."""
+    import torch
+    batch = S.workload_uneven(0)
+    assert batch.n_scenes == 512 and batch.n_goals == 118830
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 16, True)
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, 100)
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    solver.score(db, st, v_ref, cost, best)
+    torch.cuda.synchronize()
+    c = st.c.cpu().numpy()
+    cg, bg = cost.cpu().numpy(), best.cpu().numpy()
+    off = batch.goal_off()
+    # scenes: every horizon, the fewest and the most obstacles, the smallest and largest goal counts
+    keys = [(sc.n_time, sc.obs.shape[0], sc.goals.shape[0], i) for i, sc in enumerate(batch.scenes)]
+    pick = set()
+    for n in (50, 100, 150):
+        of_n = [k for k in keys if k[0] == n]
+        for key in (lambda k: k[1], lambda k: -k[1], lambda k: k[2], lambda k: -k[2]):
+            pick.add(min(of_n, key=key)[3])
+    pick = sorted(pick)[:12]
+    for i in pick:
+        sc = batch.scenes[i]
+        G = sc.goals.shape[0]
+        goals = sorted({0, G // 2, G - 1})
+        prob, ref = oracle_scene(sc, 100, goals=goals)
+        sl = [off[i] + g for g in goals]
+        print(f"scene {i}: T={sc.n_time}, m={sc.obs.shape[0]}, goals={G}")
+        check_gate(c[:, :, sl], prob, sc, ref, 100, goals=goals, max_undetermined=0.67)
+        # ranking of the scene's computed trajectories
+        sls = slice(off[i], off[i + 1])
+        rc = O.meta_cost(prob, c[0][:, sls].astype(np.float64), c[1][:, sls].astype(np.float64),
+                         c[2][:, sls].astype(np.float64), 0, v_ref=float(sc.ego[2]))
+        fin = np.isfinite(rc)
+        assert np.array_equal(np.isfinite(cg[sls]), fin)
+        assert np.allclose(cg[sls][fin], rc[fin], rtol=1e-4, atol=1e-3)
+        bo = O.best_goal(rc)
+        if bg[i] != bo:
+            assert bo >= 0 and abs(rc[bg[i]] - rc[bo]) <= 1e-4 * max(1.0, abs(rc[bo]))
+    solver.close()
