@@ -169,8 +169,9 @@ int traj_score(void *handle, const traj_batch *batch, const traj_state *state, c
 /*
  * traj_converge -- iterate until the stopping rule of Sec. IV (residuals of the
  * order 1e-3 for the trajectory that is executed): chunks of `chunk` iterations,
- * each followed by traj_score; a scene is done once its current best goal has
- * max(r_obs, r_acc, r_nh) <= tol, and later chunks skip it. At most max_iters
+ * each followed by the scoring of traj_score; a scene is done once its current
+ * best goal has max(r_obs, r_acc, r_nh) <= tol, and later chunks neither iterate
+ * nor re-score it (its state, costs and best goal stay as they were). At most max_iters
  * iterations per scene. Everything is enqueued on the stream without host
  * synchronisation (graph-capturable); the loop length is fixed by max_iters and
  * chunk, so finished scenes cost only the skipped launches.

@@ -93,7 +93,7 @@ int check_batch(const Handle* h, const traj_batch* b) {
 int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
                void* stream, bool reuse_order);
 int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
-               int32_t* best, void* stream);
+               int32_t* best, void* stream, const int32_t* skip = nullptr);
 
 }  // namespace
 
@@ -217,7 +217,9 @@ int traj_converge(void* handle, const traj_batch* batch, traj_state* state, cons
     // the first chunk starts as the caller asked; later chunks resume the state
     const uint32_t f = c == 0 ? flags : ((flags & keep) | TRAJ_INIT_FROM_STATE);
     if ((rc = solve_impl(h, batch, state, it, 0.f, f, stream, c > 0)) != TRAJ_OK) return rc;
-    if ((rc = score_impl(h, batch, state, mc, cost, best, stream)) != TRAJ_OK) return rc;
+    // scenes converged in an earlier chunk are neither iterated nor re-scored
+    if ((rc = score_impl(h, batch, state, mc, cost, best, stream, c > 0 ? state->scene_done : nullptr)) != TRAJ_OK)
+      return rc;
     if (state->resid == nullptr) return fail(TRAJ_E_INVAL, "state.resid is required");
     e = traj::launch_converge_check(batch->goal_off, state->resid, best, batch->n_scenes, batch->n_goals, it, tol,
                                     state->scene_done, scene_iters, st);
@@ -298,7 +300,7 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
 }
 
 int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
-               int32_t* best, void* stream) {
+               int32_t* best, void* stream, const int32_t* skip) {
   if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
   int rc = check_batch(h, batch);
   if (rc != TRAJ_OK) return rc;
@@ -332,6 +334,7 @@ int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, cons
   a.a = h->p.a;
   a.b = h->p.b;
   a.clear_min = mc->clear_min;
+  a.skip = skip;
   a.cost = cost;
   a.best = best;
   hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream);

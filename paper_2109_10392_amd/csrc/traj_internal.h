@@ -118,6 +118,9 @@ struct ScoreArgs {
   const int32_t* obs_off;
   const float* obs;
   float a, b, clear_min;
+  // scenes with a non-zero entry keep their cost and best untouched (NULL: none);
+  // the chunked solve passes its converged scenes, whose state no longer changes
+  const int32_t* skip;
   float* cost;
   int32_t* best;
 };

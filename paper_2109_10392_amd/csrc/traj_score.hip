@@ -60,6 +60,7 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
   const int g = blockIdx.x * COST_GOALS + (int)(threadIdx.x / COST_LANES);
   if (g >= A.n_goals) return;  // whole rows leave together
   const int s = scene_of(A.goal_off, A.n_scenes, g);
+  if (A.skip != nullptr && A.skip[s] != 0) return;
   const int sid = A.shape_id[s];
   if (sid < 0 || sid >= A.n_shapes) {
     if (r == 0) A.cost[g] = __builtin_nanf("");
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
   __shared__ float sv[SCORE_THREADS / WAVE];
   __shared__ int si[SCORE_THREADS / WAVE];
   const int s = blockIdx.x;
+  if (A.skip != nullptr && A.skip[s] != 0) return;
   const int g0 = A.goal_off[s], g1 = min((int)A.goal_off[s + 1], A.n_goals);
   float best = __builtin_inff();
   int bi = 0x7fffffff;
