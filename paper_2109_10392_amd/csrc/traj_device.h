@@ -65,6 +65,16 @@ __device__ __forceinline__ float wave_min(float v) {
 
 __device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
 
+// Minimum over each DPP row of 16 lanes, returned in every lane of the row.
+__device__ __forceinline__ float row_min(float v) {
+  v = fminf(v, dpp<DPP_QUAD_1032>(v));
+  v = fminf(v, dpp<DPP_QUAD_2301>(v));
+  v = fminf(v, dpp<DPP_ROW_HALF_MIRROR>(v));
+  return fminf(v, dpp<DPP_ROW_MIRROR>(v));
+}
+
+__device__ __forceinline__ float row_max(float v) { return -row_min(-v); }
+
 // sin and cos of |r| <= pi/2: Taylor series about 0 truncated after r^15 / r^16
 // (truncation error below 1e-11, so FP32 rounding dominates).
 __device__ __forceinline__ void sincos_taylor(float x, float* sn, float* cs) {

@@ -139,18 +139,26 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     const float sax = xdd * fa, say = ydd * fa;
     // obstacle polar variables, eqs. 15 and 22, in units scaled by (1/a, 1/b):
     // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse.
-    // Only obstacles whose box over this slot's samples (inflated by the scaled
-    // half-axes plus 0.1%) meets the slot's trajectory box are visited; for every
-    // other pair (x/a - xi_x)^2 + (y/b - xi_y)^2 > 1 holds in FP32 as well, so the
-    // result is exactly that of visiting all obstacles.
+    // Culling at the time granularity of a DPP row (16 consecutive samples): an
+    // obstacle is visited only if, for some row, its box over the row's time span
+    // (inflated by the scaled half-axes plus 0.1%) meets the box of the row's
+    // trajectory samples; for every other pair (x/a - xi_x)^2 + (y/b - xi_y)^2 > 1
+    // holds in FP32 as well, so the result is exactly that of visiting all
+    // obstacles. Whole slots (64 samples, 6.4 s) would let most obstacles of the
+    // lanes a trajectory passes through into the loop.
     const float X = x * G.inv_a, Y = y * G.inv_b;
     const float inf = __builtin_inff();
-    const float xlo = wave_min(L.val[s] ? X : inf), xhi = wave_max(L.val[s] ? X : -inf);
-    const float ylo = wave_min(L.val[s] ? Y : inf), yhi = wave_max(L.val[s] ? Y : -inf);
+    const float xlo = row_min(L.val[s] ? X : inf), xhi = row_max(L.val[s] ? X : -inf);
+    const float ylo = row_min(L.val[s] ? Y : inf), yhi = row_max(L.val[s] ? Y : -inf);
     bool hit = false;
-    if (lane < G.m) {
-      const float4 bx = box[gs * MAX_OBS + lane];
-      hit = (xhi > bx.x) && (xlo < bx.y) && (yhi > bx.z) && (ylo < bx.w);
+#pragma unroll
+    for (int rw = 0; rw < WAVE / 16; ++rw) {
+      const float rxlo = rdlane(xlo, 16 * rw), rxhi = rdlane(xhi, 16 * rw);
+      const float rylo = rdlane(ylo, 16 * rw), ryhi = rdlane(yhi, 16 * rw);
+      if (lane < G.m) {
+        const float4 bx = box[(gs * (WAVE / 16) + rw) * MAX_OBS + lane];
+        hit = hit || ((rxhi > bx.x) && (rxlo < bx.y) && (ryhi > bx.z) && (rylo < bx.w));
+      }
     }
     unsigned long long cand = __ballot(hit);
     const float tm = (float)(lane + WAVE * gs) * G.dt;
@@ -435,7 +443,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   constexpr int GPW = WPG == 1 ? GOALS_PER_WG : 1;  // goals per workgroup
   constexpr int THREADS = WAVE * WPG * GPW;
   __shared__ float4 sobs[MAX_OBS];                  // the scene's obstacles, scaled by (1/a, 1/b)
-  __shared__ float4 box[S * WPG * MAX_OBS];         // per slot and obstacle: x range, y range (scaled, inflated)
+  __shared__ float4 box[S * WPG * (WAVE / 16) * MAX_OBS];  // per slot, row of 16 samples and obstacle:
+                                                          // x range, y range (scaled, inflated)
   __shared__ double apply64[4 * NC * NC];           // MGx, Mx, MGy, My of the scene's shape
   __shared__ float ex[2 * 2 * WAVE];                // partial sums of a goal's two waves (double-buffered)
   __shared__ int sh[2];
@@ -469,19 +478,20 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
     const float* o = A.obs + 4 * (o0 + j);
     sobs[j] = make_float4(o[0] * inv_a, o[1] * inv_b, o[2] * inv_a, o[3] * inv_b);
   }
-  // Per-slot boxes: the scaled prediction fma(v', t, p') is monotone in the sample
-  // time, so its extremes over a slot are at the slot's first and last sample
-  // (the same expression the projections evaluate).
-  for (int e = tid; e < S * WPG * m; e += THREADS) {
-    const int gs = e / m, j = e - gs * m;
-    const int i0 = min(WAVE * gs, n - 1), i1 = min(WAVE * gs + WAVE - 1, n - 1);
+  // Boxes per slot row (16 samples): the scaled prediction fma(v', t, p') is
+  // monotone in the sample time, so its extremes over a row are at the row's
+  // first and last sample (the same expression the projections evaluate).
+  constexpr int ROWS = WAVE / 16;
+  for (int e = tid; e < S * WPG * ROWS * m; e += THREADS) {
+    const int gr = e / m, j = e - gr * m;  // gr = slot * ROWS + row
+    const int i0 = min(16 * gr, n - 1), i1 = min(16 * gr + 15, n - 1);
     const float* o = A.obs + 4 * (o0 + j);
     const float px = o[0] * inv_a, py = o[1] * inv_b, vx = o[2] * inv_a, vy = o[3] * inv_b;
     const float t0 = (float)i0 * dt, t1 = (float)i1 * dt;
     const float xa = fmaf(vx, t0, px), xb = fmaf(vx, t1, px);
     const float ya = fmaf(vy, t0, py), yb = fmaf(vy, t1, py);
     constexpr float R = 1.001f;
-    box[gs * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
+    box[gr * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
   }
   const double* T64 = A.tables64 + sd.table64_off;
   for (int e = tid; e < NC * NC; e += THREADS) {
