@@ -33,13 +33,13 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "011bf7b28039e34c098b6f05867278ebae5c174a2b0862761f573a4057061b58",
-              "bytes_per_launch": int((263.0 * 2.0 + 2272.0) * 1024),
+              "sha256": "d6060d209c5643b9841620b9190f67c15f12cbf2082da25902e8829a1e875af5",
+              "bytes_per_launch": int((269.5 * 2.0 + 2272.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "0ac32428f345b367e19f280085a47a5bcd92f6b88b2d819a9d3f262fdf3ff9cd",
-               "bytes_per_launch": int((79314.8 * 2.0 + 277566.7) * 1024),
+               "sha256": "62cdb7c4c04577ecd179193070743a77252e509e81624bfbc4851336f55344f2",
+               "bytes_per_launch": int((85788.3 * 2.0 + 277103.8) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
