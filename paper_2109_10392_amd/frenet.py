@@ -48,7 +48,6 @@ class Road:
 
     def from_global(self, states, out=None, stream=None):
         """[n][4] (x, y, vx, vy) or [n][8] ego states -> the road frame (same width)."""
-        import torch
         kind = {4: 0, 8: 1}[int(states.shape[-1])]
         out = states if out is None else out
         r = self.c_struct()

@@ -13,8 +13,6 @@ from __future__ import annotations
 
 import ctypes
 
-import numpy as np
-
 from . import scenes as S
 from . import traj as T
 

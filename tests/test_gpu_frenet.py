@@ -7,7 +7,6 @@ import math
 import numpy as np
 import pytest
 
-from oracle import traj_oracle as O
 from oracle.frenet_oracle import RoadOracle
 from paper_2109_10392_amd import scenes as S
 from tests.test_gpu_parity import PARAMS

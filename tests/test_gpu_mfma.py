@@ -15,7 +15,7 @@ import pytest
 
 from oracle import traj_oracle as O
 from paper_2109_10392_amd import scenes as S
-from tests.test_gpu_parity import (PARAMS, TOL, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
+from tests.test_gpu_parity import (TOL, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
                                    undetermined_goals)
 
 pytestmark = pytest.mark.gpu

@@ -5,7 +5,6 @@ import numpy as np
 import pytest
 
 from oracle import traj_oracle as O
-from paper_2109_10392_amd import scenes as S
 from tests.test_gpu_parity import PARAMS
 
 pytestmark = pytest.mark.gpu
