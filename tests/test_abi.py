@@ -112,3 +112,23 @@ def test_road_is_validated_on_the_host():
     assert L.traj_road_from_global(ctypes.byref(good.c_struct()), 2, 1, None, None, None) == -1
     assert L.traj_road_from_global(ctypes.byref(good.c_struct()), 0, 0, None, None, None) == 0
     assert L.traj_road_to_global(ctypes.byref(good.c_struct()), 0, None, None, None) == 0
+
+
+def test_closed_loop_calls_validate_on_the_host():
+    """Bad arguments of the closed-loop calls are rejected before anything is launched."""
+    from paper_2109_10392_amd import mpc as M
+    L = M._bind()
+    b, st, eps = T.BatchC(), T.StateC(), M.EpisodesC()
+    good = M.params()
+    bad = [M.params(idm_a=0.0), M.params(n_lanes=0), M.params(per_lane=0), M.params(sampler=2),
+           M.params(sampler=1, v_max=0.0), M.params(lane_width=-1.0)]
+    for p in bad:
+        assert L.traj_mpc_goals(None, ctypes.byref(b), ctypes.byref(eps), ctypes.byref(p), None) == -1
+        assert L.traj_mpc_step(None, ctypes.byref(b), ctypes.byref(st), None, ctypes.byref(eps), ctypes.byref(p), 0,
+                               None) == -1
+    # NULL arrays / handle with valid parameters
+    assert L.traj_mpc_goals(None, ctypes.byref(b), ctypes.byref(eps), ctypes.byref(good), None) == -1
+    assert L.traj_mpc_step(None, ctypes.byref(b), ctypes.byref(st), None, ctypes.byref(eps), ctypes.byref(good), 0,
+                           None) == -1
+    assert L.traj_mpc_shift(None, ctypes.byref(b), ctypes.byref(st), ctypes.byref(eps), None) == -1
+    assert L.traj_last_error()
