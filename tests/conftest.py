@@ -10,3 +10,11 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
+
+
+def report_path(name):
+    """Where GPU tests write their JSON reports: $TRAJ_REPORT_DIR (default
+    test_reports/ at the repository root), created on demand."""
+    d = os.environ.get("TRAJ_REPORT_DIR", os.path.join(ROOT, "test_reports"))
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, name)

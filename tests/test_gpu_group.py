@@ -6,10 +6,11 @@ columns, so the group size and the schedule (list order or persistent claiming)
 must not change any bit of the result when no tolerance stop is used.
 """
 import json
-import os
 
 import numpy as np
 import pytest
+
+from tests.conftest import report_path
 
 from oracle import traj_oracle as O
 from paper_2109_10392_amd import scenes as S
@@ -214,8 +215,7 @@ def test_bf16x3_group_precision_report(T):
                          resid_abs_err_max=float(res_err[~und].max()), best_gpu=bg, best_oracle=bo,
                          best_match=bool(near), undetermined=np.flatnonzero(und).tolist()))
         print(json.dumps(rows[-1]))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "bf16x3_group_precision_report.json"), "w") as f:
+    with open(report_path("bf16x3_group_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9
 

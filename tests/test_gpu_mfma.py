@@ -8,10 +8,11 @@ scene, and the test checks that they are finite and that the best goal is the
 oracle's (or a near-tie).
 """
 import json
-import os
 
 import numpy as np
 import pytest
+
+from tests.conftest import report_path
 
 from oracle import traj_oracle as O
 from paper_2109_10392_amd import scenes as S
@@ -118,7 +119,6 @@ def test_bf16x3_precision_report(T):
                          resid_abs_err_max=float(res_err[~und].max()), best_gpu=bg, best_oracle=bo,
                          best_match=bool(near), undetermined=np.flatnonzero(und).tolist()))
         print(json.dumps(rows[-1]))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "bf16x3_precision_report.json"), "w") as f:
+    with open(report_path("bf16x3_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9

@@ -7,14 +7,15 @@ checked every 5 iterations, at most 300) on 512 unseen scenes from the cold
 start and from the network's prediction (with the cold start as per-goal
 fallback after one iteration). The warm start must need fewer iterations on
 average at the same FP32 precision; the report (iterations, converged fraction,
-ms per scene, also for the split-BF16 solver) goes to
-gpurun_out/warmstart_report.json.
+ms per scene, also for the split-BF16 solver) goes to warmstart_report.json in
+the test report directory.
 """
 import json
-import os
 
 import numpy as np
 import pytest
+
+from tests.conftest import report_path
 
 pytestmark = pytest.mark.gpu
 
@@ -31,8 +32,7 @@ def test_trained_warm_start_needs_fewer_iterations():
     res = W.evaluate(prob, net, mean, std, list(range(512)))
     res["training"] = info
     print(json.dumps(res, indent=1))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "warmstart_report.json"), "w") as f:
+    with open(report_path("warmstart_report.json"), "w") as f:
         json.dump(res, f, indent=1)
     assert res["warm_fp32"]["iters_mean"] < 0.97 * res["cold"]["iters_mean"]
     assert res["warm"]["iters_mean"] < res["cold"]["iters_mean"]
