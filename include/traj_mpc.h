@@ -71,7 +71,8 @@ int traj_mpc_goals(void *handle, const traj_batch *batch, const traj_episodes *e
  * IDM (following the nearest vehicle ahead in its lane, the ego included; free
  * road otherwise; speed clipped at 0, ballistic position update); the ego to its
  * chosen trajectory one sample ahead (state c of goal best[s]; with best[s] < 0
- * it holds its heading and brakes at a_max); then the frame re-centred on the
+ * it brakes along the road at a_max (x' -= a_max dt, floored at 0) and stops
+ * moving sideways: y kept, y' = y'' = psi = psi' = 0); then the frame re-centred on the
  * ego and overlaps of obstacle ellipses with the ego centre counted.
  *   n_obs: total obstacles of the batch (= obs_off[n_scenes]).
  */

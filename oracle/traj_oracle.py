@@ -481,6 +481,17 @@ def idm_step(obs, ego, v_des, dt, p):
     return out
 
 
+def ego_brake(ego, a_max, dt):
+    """The ego's fallback when every goal is filtered: it brakes along the road at
+    a_max (longitudinal speed floored at zero, the distance covered at the mean of
+    the two speeds) and stops moving sideways at its lateral position."""
+    ego = np.asarray(ego, np.float64)
+    vx = max(ego[2], 0.0)
+    vx_new = max(vx - a_max * dt, 0.0)
+    return np.array([ego[0] + 0.5 * (vx + vx_new) * dt, ego[1], vx_new, 0.0,
+                     -a_max if vx_new < vx else 0.0, 0.0, 0.0, 0.0])
+
+
 def shift_matrix(n_coef, u0):
     """S with c' = S c: the Bernstein coefficients, on [0, 1], of the polynomial
     u -> sum_k c_k B_k(u0 + u), i.e. the same trajectory seen from a horizon that

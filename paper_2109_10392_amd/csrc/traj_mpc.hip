@@ -167,16 +167,18 @@ __global__ void k_mpc_ego(MpcArgs A) {
       ne[7] = fmaf(pd, cp, ne[7]);
     }
   } else {
-    // every goal filtered: hold the heading and brake at a_max
-    const float v = sqrtf(fmaf(e[2], e[2], e[3] * e[3]));
-    const float v_new = fmaxf(v - A.a_max * dt, 0.f);
-    const float f = v > 0.f ? v_new / v : 0.f;
-    ne[0] = e[0] + 0.5f * (1.f + f) * e[2] * dt;
-    ne[1] = e[1] + 0.5f * (1.f + f) * e[3] * dt;
-    ne[2] = e[2] * f;
-    ne[3] = e[3] * f;
-    ne[4] = ne[5] = 0.f;
-    ne[6] = e[6];
+    // every goal filtered: brake along the road at a_max and stop moving
+    // sideways (holding a lane change's heading would carry the ego into the
+    // vehicle alongside)
+    const float vx = fmaxf(e[2], 0.f);
+    const float vx_new = fmaxf(vx - A.a_max * dt, 0.f);
+    ne[0] = e[0] + 0.5f * (vx + vx_new) * dt;
+    ne[1] = e[1];
+    ne[2] = vx_new;
+    ne[3] = 0.f;
+    ne[4] = vx_new < vx ? -A.a_max : 0.f;
+    ne[5] = 0.f;
+    ne[6] = 0.f;
     ne[7] = 0.f;
     A.e.fallbacks[s] += 1;
   }

@@ -13,6 +13,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 from . import scenes as S
 from . import traj as T
 
@@ -101,6 +103,12 @@ class ClosedLoop:
         self.p = params(sampler=self.kind, v_max=v_max)
         # closed-loop statistics, accumulated on the device every cycle
         self.stats = {k: z(n_s) for k in ("v_res", "v_res_max", "lat", "acc", "acc_max", "ang", "ang_max")}
+        # closest approach: smallest scaled distance sqrt((dx/a)^2 + (dy/b)^2) of any
+        # obstacle centre to the ego after a cycle (below 1: inside the inflated ellipse)
+        self.closest = torch.full((n_s,), float("inf"), device="cuda")
+        self.obs_scene = torch.repeat_interleave(torch.arange(n_s, device="cuda"),
+                                                 torch.tensor(np.diff(self.batch.obs_off()), device="cuda"))
+        self.ell = (float(S.DEFAULT_PARAMS["a"]), float(S.DEFAULT_PARAMS["b"]))
         self.psid_prev = self.db.ego[:, 7].clone()
         self.precision, self.iters, self.tol, self.net = precision, iters, tol, net
         if warm not in ("cold", "previous", "shifted", "learned"):
@@ -174,6 +182,10 @@ class ClosedLoop:
         st["ang"] += ang
         torch.maximum(st["ang_max"], ang, out=st["ang_max"])
         self.psid_prev.copy_(e[:, 7])
+        if self.n_obs > 0:
+            o = self.db.obs[: self.n_obs]
+            q = torch.hypot(o[:, 0] / self.ell[0], (o[:, 1] - e[self.obs_scene, 1]) / self.ell[1])
+            self.closest.scatter_reduce_(0, self.obs_scene, q, reduce="amin")
 
     @property
     def period(self):
@@ -198,6 +210,7 @@ class ClosedLoop:
                 "right_lane_distance_mean": float(st["lat"].mean() / c),
                 "linear_acc_mean": float(st["acc"].mean() / c), "linear_acc_max": float(st["acc_max"].max()),
                 "angular_acc_mean": float(st["ang"].mean() / c), "angular_acc_max": float(st["ang_max"].max()),
+                "closest_approach": float(self.closest.min().item()),
                 "collision_events": int(self.collisions.sum().item()),
                 "episodes_with_collision": int((self.collisions > 0).sum().item()),
                 "fallback_cycles": int(self.fallbacks.sum().item()),

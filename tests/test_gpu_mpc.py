@@ -144,3 +144,35 @@ def test_right_lane_closed_loop_run(M):
     print(m)
     assert np.all(np.isfinite(cl.db.ego.cpu().numpy()))
     assert m["mean_speed"] > 5.0 and np.isfinite(m["right_lane_distance_mean"])
+
+
+def test_brake_fallback_matches_the_oracle(M):
+    """Episodes whose goals are all filtered (best < 0) brake along the road and
+    stop moving sideways; the others advance along their plans."""
+    import torch
+    cl = M.ClosedLoop(range(12), iters=10)
+    rng = np.random.default_rng(6)
+    ego = cl.db.ego.cpu().numpy()
+    ego[:, 3] = rng.normal(0, 0.5, ego.shape[0])
+    ego[:, 1] = rng.normal(0, 0.8, ego.shape[0])
+    ego[5, 2] = 0.1  # stops within the period
+    cl.db.ego.copy_(torch.from_numpy(ego))
+    cl.goals()
+    cl.plan()
+    best = cl.best.cpu().numpy()
+    forced = [0, 3, 5, 11]
+    best[forced] = -1
+    cl.best.copy_(torch.from_numpy(best))
+    ego0 = cl.db.ego.cpu().numpy().astype(np.float64)
+    fb0 = cl.fallbacks.cpu().numpy().copy()
+    cl.step()
+    torch.cuda.synchronize()
+    ego1, tr = cl.db.ego.cpu().numpy(), cl.travelled.cpu().numpy()
+    dt = cl.period
+    for s in forced:
+        ref = O.ego_brake(ego0[s], 4.0, dt)
+        assert abs(tr[s] - ref[0]) <= 1e-5 * max(1.0, ref[0]), s
+        ref[0] = 0.0
+        assert np.allclose(ego1[s], ref, rtol=1e-5, atol=1e-5), (s, ego1[s], ref)
+    fb = cl.fallbacks.cpu().numpy()
+    assert np.array_equal(fb - fb0, np.isin(np.arange(12), forced).astype(fb.dtype))

@@ -127,3 +127,13 @@ def test_right_lane_sampler_counts_and_distances():
         assert sel.sum() in (34, 35)
         assert np.all((g[sel, 0] >= 1.0 + 0.9 * 250.0 - 1e-9) & (g[sel, 0] <= 1.0 + 250.0 + 1e-9))
     assert len({tuple(r) for r in g}) == 256
+
+
+def test_brake_fallback():
+    dt, a = 0.1, 4.0
+    e = O.ego_brake([0.0, 1.2, 15.0, 0.8, 0.3, -0.2, 0.05, 0.01], a, dt)
+    assert np.allclose(e, [0.5 * (15.0 + 14.6) * dt, 1.2, 14.6, 0, -4.0, 0, 0, 0])
+    # at standstill it stays put; a speed below a_max dt stops within the period
+    assert np.allclose(O.ego_brake([0.0, -3.5, 0.0, 0.0, 0, 0, 0, 0], a, dt), [0, -3.5, 0, 0, 0, 0, 0, 0])
+    e = O.ego_brake([0.0, 0.0, 0.2, 0.0, 0, 0, 0, 0], a, dt)
+    assert np.allclose(e, [0.5 * 0.2 * dt, 0, 0, 0, -4.0, 0, 0, 0])
