@@ -137,7 +137,13 @@ int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes
  *   flags: TRAJ_INIT_COLD or TRAJ_INIT_FROM_STATE, | TRAJ_PREC_FP32 or
  *          TRAJ_PREC_BF16X3, | TRAJ_KERNEL_AUTO, TRAJ_KERNEL_WAVE,
  *          TRAJ_KERNEL_MFMA or TRAJ_KERNEL_GROUP (BF16X3 runs on a matrix-core
- *          kernel: the group kernel if asked for, else the MFMA kernel).
+ *          kernel: the group kernel if asked for, else the MFMA kernel). The
+ *          MFMA kernel holds the obstacle predictions of a whole horizon in LDS:
+ *          n_tiles (144 n_obs + 4096) bytes (n_tiles = ceil(n_time / 16), from
+ *          the handle's longest horizon and largest obstacle count) must stay
+ *          within 150 KiB, e.g. n_time <= 176 with 64 obstacles; larger handles
+ *          get TRAJ_E_INVAL for it (the wave and group kernels take every shape
+ *          traj_setup accepts).
  *   tol: <= 0 runs exactly `iters` iterations; > 0 stops at the first multiple
  *        of 5 iterations where max(r_obs, r_acc, r_nh) <= tol: per goal in the
  *        wave kernel, per goal group (all of its goals) in the matrix-core kernels.

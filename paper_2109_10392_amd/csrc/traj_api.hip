@@ -291,6 +291,13 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
     e = traj::launch_solve_group(a, mode, h->tile.group, h->tile.persistent != 0, h->resident_blocks[mode],
                                  state->work, reuse_order, (hipStream_t)stream);
   } else if (kernel == TRAJ_KERNEL_MFMA) {
+    const size_t need = traj::mfma_smem_bytes(h->max_n, h->max_m);
+    if (need > traj::MFMA_SMEM_LIMIT)
+      return fail(TRAJ_E_INVAL,
+                  "the MFMA kernel keeps every obstacle prediction of a horizon in LDS: the handle's longest "
+                  "horizon (%d samples) with its most obstacles (%d) needs %zu bytes > %zu; use the group or "
+                  "the wave kernel",
+                  h->max_n, h->max_m, need, traj::MFMA_SMEM_LIMIT);
     e = traj::launch_solve_mfma(a, mode, h->tile.group, h->max_n, h->max_m, (hipStream_t)stream);
   } else {
     e = traj::launch_solve(a, h->max_n, h->max_m, h->tile.waves, (hipStream_t)stream);

@@ -150,6 +150,7 @@ hipError_t launch_setup(const ShapeDesc* d_shapes, int n_shapes, const SolverCon
 hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, int waves, hipStream_t stream);
 hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
 size_t mfma_smem_bytes(int max_n, int max_m);
+constexpr size_t MFMA_SMEM_LIMIT = 150 * 1024;  // LDS the MFMA kernel may take per workgroup
 hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
 hipError_t launch_controls(const ControlArgs& a, hipStream_t stream);
 

@@ -463,7 +463,7 @@ hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int
   const int W = (max_n + TILE - 1) / TILE;
   const int blocks = (a.n_goals + G - 1) / G + a.n_scenes;
   const size_t smem = mfma_smem_bytes(max_n, max_m);
-  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  if (smem > MFMA_SMEM_LIMIT) return hipErrorInvalidValue;
   const void* fn = mode == TRAJ_MODE_BF16X3 ? (const void*)k_am_mfma<TRAJ_MODE_BF16X3>
                                             : (const void*)k_am_mfma<TRAJ_MODE_FP32>;
   if (smem > 65536) {

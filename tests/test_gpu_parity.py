@@ -302,3 +302,40 @@ def test_score_matches_oracle(T):
             if bg[i] != bo:
                 assert bo >= 0 and abs(ref[bg[i]] - ref[bo]) <= 1e-4 * max(1.0, abs(ref[bo]))
     solver.close()
+
+
+@pytest.mark.parametrize("tile", [("wave", 1, 192), ("wave", 2, 192), ("group", 1, 192), ("mfma", 1, 176)])
+def test_largest_horizon_and_obstacle_count(T, tile):
+    """The largest shape each kernel takes with 64 obstacles against the oracle:
+    n_time = 192 (the handle's limit, three 64-lane slots) on the wave and group
+    kernels, 176 on the MFMA kernel (its LDS budget)."""
+    kernel, waves, n = tile
+    sc = S.make_scene(17, n_goals=6, n_obs=64, n_lanes=6, n_time=n, t_f=(n - 1) / 10.0)
+    batch = S.Batch([sc])
+    out = gpu_solve(T, batch, 60, kernel=kernel, waves=waves)
+    prob, st = oracle_scene(sc, 60)
+    print(f"n={n}, m=64, {tile}:")
+    check_gate(out["c"], prob, sc, st, 60, max_undetermined=0.5)
+
+
+@pytest.mark.parametrize("tile", [("wave", 1), ("group", 1)])
+def test_smallest_horizon_is_valid(T, tile):
+    """n_time = 11 (as many samples as coefficients; the x/y system's condition
+    number is ~6e7, so FP32 is not held to the 1e-4 gate): finite iterates that
+    meet the boundary rows."""
+    kernel, waves = tile
+    sc = S.make_scene(18, n_goals=5, n_obs=4, n_lanes=4, n_time=11, t_f=1.0)
+    batch = S.Batch([sc])
+    out = gpu_solve(T, batch, 30, kernel=kernel, waves=waves)
+    assert np.all(np.isfinite(out["c"]))
+    prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+    b_x, b_y, b_psi = O.boundary_values(sc.ego, sc.goals)
+    c = out["c"].astype(np.float64)
+    for A, ax, b in ((prob.A_x, 0, b_x), (prob.A_y, 1, b_y), (prob.A_psi, 2, b_psi)):
+        assert np.max(np.abs(A @ c[ax] - b)) <= 1e-2 * max(1.0, np.max(np.abs(b)))
+
+
+def test_mfma_kernel_rejects_a_horizon_beyond_its_lds_budget(T):
+    sc = S.make_scene(17, n_goals=3, n_obs=64, n_lanes=6, n_time=192, t_f=19.1)
+    with pytest.raises(T.TrajError, match="MFMA kernel keeps every obstacle prediction"):
+        gpu_solve(T, S.Batch([sc]), 5, kernel="mfma")
