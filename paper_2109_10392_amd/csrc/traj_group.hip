@@ -361,29 +361,35 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   __builtin_amdgcn_wave_barrier();
   const float4* obs = sobs;
 
-  // The apply operators (up to 40 registers per lane) are read from the tables
-  // (cache-resident) at each use instead of being held across the sweeps: the
-  // addresses carry an offset the compiler cannot see through (an empty asm
+  // The apply operators (16 FP64 values per axis and lane) are read from the
+  // tables (cache-resident) at each use instead of being held across the sweeps:
+  // the addresses carry an offset the compiler cannot see through (an empty asm
   // statement), so the loop-invariant loads are not hoisted out of the loop.
-  auto apply_ops = [&]() {
+  auto opaque_offset = []() {
     int opaque = 0;
     asm volatile("" : "+v"(opaque));
-    ApplyOps<MODE> ap;
-    load_apply_ops<MODE>(ap, T + opaque, T64 + opaque, n, j, q);
-    return ap;
+    return opaque;
+  };
+  auto xy_ops = [&](int axis) {
+    XYOps o;
+    load_xy_ops(o, T64 + opaque_offset(), axis, j, q);
+    return o;
+  };
+  auto psi_ops = [&]() {
+    PsiOps<MODE> o;
+    load_psi_ops<MODE>(o, T + opaque_offset(), n, j, q);
+    return o;
   };
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
   f4 cx = zero, cy = zero, cp = zero, lx = zero, ly = zero, lp = zero;
   const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
   Particular P;
   particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, cold, cx, cy);
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-    // the FP64 particular parts wait in LDS between applies ([axis][r][lane])
+  // the FP64 particular parts wait in LDS between applies ([axis][r][lane])
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      sc0[(0 * 4 + r) * WAVE + lane] = P.c0xd[r];
-      sc0[(1 * 4 + r) * WAVE + lane] = P.c0yd[r];
-    }
+  for (int r = 0; r < 4; ++r) {
+    sc0[(0 * 4 + r) * WAVE + lane] = P.c0xd[r];
+    sc0[(1 * 4 + r) * WAVE + lane] = P.c0yd[r];
   }
   auto c0d = [&](int axis) {
     d4 v;
@@ -510,24 +516,16 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   // d), (alpha_a, d_a); no multiplier is updated here
   auto start = [&](bool cold_start) {
     const f4 W = heading_sweep();
-    if (cold_start) cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
+    if (cold_start) cp = apply_psi<MODE>(psi_ops(), P.c0p, rho * W + lp);
     projection_sweep(ux, uy, E);
   };
   auto iteration = [&]() {
     // x/y step (eq. 12 through eq. 18)
-    {
-      const ApplyOps<MODE> ap = apply_ops();
-      if constexpr (MODE == TRAJ_MODE_FP32) {
-        cx = apply_xy<MODE>(ap, 0, c0d(0), P.c0xf, cx, rho * ux + lx);
-        cy = apply_xy<MODE>(ap, 1, c0d(1), P.c0yf, cy, rho * uy + ly);
-      } else {
-        cx = apply_xy<MODE>(ap, 0, P.c0xd, P.c0xf, cx, rho * ux + lx);
-        cy = apply_xy<MODE>(ap, 1, P.c0yd, P.c0yf, cy, rho * uy + ly);
-      }
-    }
+    cx = apply_xy(xy_ops(0), c0d(0), cx, rho * ux + lx);
+    cy = apply_xy(xy_ops(1), c0d(1), cy, rho * uy + ly);
     // heading step (eq. 13 through eq. 20)
     const f4 W = heading_sweep();
-    cp = apply_psi<MODE>(apply_ops(), P.c0p, rho * W + lp);
+    cp = apply_psi<MODE>(psi_ops(), P.c0p, rho * W + lp);
     // v, (alpha, d), (alpha_a, d_a), then the multipliers (eqs. 23, 24)
     projection_sweep(ux, uy, E);
     lx = lx + rho * ux;

@@ -39,7 +39,7 @@ template <int MODE>
 struct Ops {
   Operand<MODE> ev[3];  // P, P', P'' [t = 16w + j][4q + kk]
   Operand<MODE> ct[3];  // P, P', P'' [16w + 4q + r][j]
-  ApplyOps<MODE> ap;
+  PsiOps<MODE> psi;     // the x/y operators (FP64) are read from the tables at each use
 };
 
 template <int MODE>
@@ -89,7 +89,7 @@ __device__ void load_ops(Ops<MODE>& O, const float* __restrict__ T, const double
     make_operand<MODE>(O.ev[mi], ev);
     make_operand<MODE>(O.ct[mi], ct);
   }
-  load_apply_ops<MODE>(O.ap, T, T64, n, j, q);
+  load_psi_ops<MODE>(O.psi, T, n, j, q);
 }
 
 // Per-sample closed forms for the lane's 4 samples and the contraction inputs.
@@ -279,8 +279,8 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   const float bp[NP] = {e[6], e[7], 0.f, 0.f};
   const float* Bt = T + tab_bnd(n);
   d4 c0xd = {0.0, 0.0, 0.0, 0.0}, c0yd = {0.0, 0.0, 0.0, 0.0};
-  f4 c0xf = {0.f, 0.f, 0.f, 0.f}, c0yf = c0xf, c0p = c0xf;
-  f4 cx = c0xf, cy = c0xf, cp = c0xf, lx = c0xf, ly = c0xf, lp = c0xf;
+  f4 c0p = {0.f, 0.f, 0.f, 0.f};
+  f4 cx = c0p, cy = c0p, cp = c0p, lx = c0p, ly = c0p, lp = c0p;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int k = 4 * q + r;
@@ -290,8 +290,6 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
       for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
       c0xd[r] = sx;
       c0yd[r] = sy;
-      c0xf[r] = (float)sx;
-      c0yf[r] = (float)sy;
       float sp = 0.f;
       for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
       c0p[r] = sp;
@@ -385,7 +383,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   {
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
-    if (cold) cp = apply_psi<MODE>(O.ap, c0p, rho * W_ + lp);
+    if (cold) cp = apply_psi<MODE>(O.psi, c0p, rho * W_ + lp);
     project(xd, yd, th);
     ep = zero;  // the start has no pending heading multiplier step
   }
@@ -393,13 +391,21 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   bool stopped = false;
   for (int it = 0; it < A.iters; ++it) {
     // x/y step (eq. 12 through eq. 18)
-    cx = apply_xy<MODE>(O.ap, 0, c0xd, c0xf, cx, rho * ux + lx);
-    cy = apply_xy<MODE>(O.ap, 1, c0yd, c0yf, cy, rho * uy + ly);
+    {
+      // an offset the compiler cannot see through keeps the loop-invariant loads in the loop
+      int opaque = 0;
+      asm volatile("" : "+v"(opaque));
+      XYOps o;
+      load_xy_ops(o, T64 + opaque, 0, j, q);
+      cx = apply_xy(o, c0xd, cx, rho * ux + lx);
+      load_xy_ops(o, T64 + opaque, 1, j, q);
+      cy = apply_xy(o, c0yd, cy, rho * uy + ly);
+    }
     // pending heading multiplier (eq. 24) and heading step (eq. 13 through eq. 20)
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
     lp = lp + rho * E_;
-    cp = apply_psi<MODE>(O.ap, c0p, rho * W_ + lp);
+    cp = apply_psi<MODE>(O.psi, c0p, rho * W_ + lp);
     // v, (alpha, d), (alpha_a, d_a) and u~ (eqs. 14-16, 21, 22)
     project(xd, yd, th);
     // multipliers of the x/y block (eq. 23)

@@ -117,85 +117,69 @@ __device__ __forceinline__ f4 contract(const Operand<MODE>& a, const f4& s, f4 a
 }
 
 // Operators of the x/y and heading applies (rows of the lane's column).
+//
+// The x/y step's constant operators are FP64 in both forms: they act on
+// coefficients of hundreds of metres, and their rounding is integrated by the
+// multipliers (eqs. 23, 24) over the iterations.
+struct XYOps {
+  double mg[4], m[4];  // rows permuted for the f64 output layout
+};
 template <int MODE>
-struct ApplyOps;
+struct PsiOps;
 template <>
-struct ApplyOps<TRAJ_MODE_FP32> {
-  double mgx[4], mx[4], mgy[4], my[4];  // rows permuted for the f64 output layout
+struct PsiOps<TRAJ_MODE_FP32> {
   float mp[4];
 };
 template <>
-struct ApplyOps<TRAJ_MODE_BF16X3> {
-  bf8 mgx[2], mx[2], mgy[2], my[2], mp[2];
+struct PsiOps<TRAJ_MODE_BF16X3> {
+  bf8 mp[2];
 };
 
+__device__ __forceinline__ void load_xy_ops(XYOps& O, const double* __restrict__ T64, int axis, int j, int q) {
+  // row permutation of the f64 16x16x4 output: register r of row group q is row 4r + q
+  const int prow = 4 * (j & 3) + (j >> 2);
+  const double* mg = T64 + (axis == 0 ? T64_MGX : T64_MGY);
+  const double* m = T64 + (axis == 0 ? T64_MX : T64_MY);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * q + kk;
+    const bool ok = prow < NC && k < NC;
+    O.mg[kk] = ok ? mg[prow * NC + k] : 0.0;
+    O.m[kk] = ok ? m[prow * NC + k] : 0.0;
+  }
+}
+
 template <int MODE>
-__device__ __forceinline__ void load_apply_ops(ApplyOps<MODE>& O, const float* __restrict__ T,
-                                               const double* __restrict__ T64, int n, int j, int q) {
+__device__ __forceinline__ void load_psi_ops(PsiOps<MODE>& O, const float* __restrict__ T, int n, int j, int q) {
+  float mp[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * q + kk;
+    mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
+  }
   if constexpr (MODE == TRAJ_MODE_FP32) {
-    // row permutation of the f64 16x16x4 output: register r of row group q is row 4r + q
-    const int prow = 4 * (j & 3) + (j >> 2);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * q + kk;
-      const bool ok = prow < NC && k < NC;
-      O.mgx[kk] = ok ? T64[T64_MGX + prow * NC + k] : 0.0;
-      O.mx[kk] = ok ? T64[T64_MX + prow * NC + k] : 0.0;
-      O.mgy[kk] = ok ? T64[T64_MGY + prow * NC + k] : 0.0;
-      O.my[kk] = ok ? T64[T64_MY + prow * NC + k] : 0.0;
-      O.mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
-    }
+    for (int kk = 0; kk < 4; ++kk) O.mp[kk] = mp[kk];
   } else {
-    float mgx[4], mx[4], mgy[4], my[4], mp[4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * q + kk;
-      const bool ok = j < NC && k < NC;
-      mgx[kk] = ok ? (float)T64[T64_MGX + j * NC + k] : 0.f;
-      mx[kk] = ok ? (float)T64[T64_MX + j * NC + k] : 0.f;
-      mgy[kk] = ok ? (float)T64[T64_MGY + j * NC + k] : 0.f;
-      my[kk] = ok ? (float)T64[T64_MY + j * NC + k] : 0.f;
-      mp[kk] = ok ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
-    }
-    split_a(mgx, O.mgx[0], O.mgx[1]);
-    split_a(mx, O.mx[0], O.mx[1]);
-    split_a(mgy, O.mgy[0], O.mgy[1]);
-    split_a(my, O.my[0], O.my[1]);
     split_a(mp, O.mp[0], O.mp[1]);
   }
 }
 
-// c0 + MG c + M r for one axis
-template <int MODE>
-__device__ __forceinline__ f4 apply_xy(const ApplyOps<MODE>& O, int axis, const d4& c0d, const f4& c0f, const f4& c,
-                                       const f4& r) {
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-    const double* mg = axis == 0 ? O.mgx : O.mgy;
-    const double* m = axis == 0 ? O.mx : O.my;
-    d4 acc = c0d;
+// c0 + MG c + M r for one axis, accumulated in FP64
+__device__ __forceinline__ f4 apply_xy(const XYOps& O, const d4& c0d, const f4& c, const f4& r) {
+  d4 acc = c0d;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma64(mg[kk], (double)c[kk], acc);
+  for (int kk = 0; kk < 4; ++kk) acc = mma64(O.mg[kk], (double)c[kk], acc);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma64(m[kk], (double)r[kk], acc);
-    f4 out;
+  for (int kk = 0; kk < 4; ++kk) acc = mma64(O.m[kk], (double)r[kk], acc);
+  f4 out;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = (float)acc[k];
-    return out;
-  } else {
-    const bf8* mg = axis == 0 ? O.mgx : O.mgy;
-    const bf8* m = axis == 0 ? O.mx : O.my;
-    const bf8 cb = split_b(c), rb = split_b(r);
-    f4 acc = c0f;
-    acc = mmabf(mg[0], cb, acc);
-    acc = mmabf(mg[1], cb, acc);
-    acc = mmabf(m[0], rb, acc);
-    acc = mmabf(m[1], rb, acc);
-    return acc;
-  }
+  for (int k = 0; k < 4; ++k) out[k] = (float)acc[k];
+  return out;
 }
 
 template <int MODE>
-__device__ __forceinline__ f4 apply_psi(const ApplyOps<MODE>& O, const f4& c0p, const f4& r) {
+__device__ __forceinline__ f4 apply_psi(const PsiOps<MODE>& O, const f4& c0p, const f4& r) {
   f4 acc = c0p;
   if constexpr (MODE == TRAJ_MODE_FP32) {
 #pragma unroll
@@ -231,7 +215,7 @@ __device__ __forceinline__ float sum_rows(float v) {
 // minimum-acceleration start.
 struct Particular {
   d4 c0xd, c0yd;
-  f4 c0xf, c0yf, c0p;
+  f4 c0p;
 };
 
 __device__ __forceinline__ void particular(const float* __restrict__ T, const double* __restrict__ T64, int n,
@@ -246,8 +230,6 @@ __device__ __forceinline__ void particular(const float* __restrict__ T, const do
     const int k = 4 * q + r;
     P.c0xd[r] = 0.0;
     P.c0yd[r] = 0.0;
-    P.c0xf[r] = 0.f;
-    P.c0yf[r] = 0.f;
     P.c0p[r] = 0.f;
     if (k < NC) {
       double sx = 0.0, sy = 0.0;
@@ -255,8 +237,6 @@ __device__ __forceinline__ void particular(const float* __restrict__ T, const do
       for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
       P.c0xd[r] = sx;
       P.c0yd[r] = sy;
-      P.c0xf[r] = (float)sx;
-      P.c0yf[r] = (float)sy;
       float sp = 0.f;
       for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
       P.c0p[r] = sp;
