@@ -376,8 +376,8 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     return o;
   };
   auto psi_ops = [&]() {
-    PsiOps<MODE> o;
-    load_psi_ops<MODE>(o, T + opaque_offset(), n, j, q);
+    PsiOps o;
+    load_psi_ops(o, T + opaque_offset(), n, j, q);
     return o;
   };
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -430,15 +430,18 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
         nd = pk[((w + 1) * PACK_SLOTS + 1) * WAVE + lane];
         np = pk[((w + 1) * PACK_SLOTS + 3) * WAVE + lane];
       }
-      Operand<MODE> evd, ctp;
+      // the heading input is contracted in FP32 in both forms (it feeds the heading
+      // operator, whose products cancel)
+      Operand<MODE> evd;
+      Operand<TRAJ_MODE_FP32> ctp;
       to_operand<MODE>(evd, vd);
-      to_operand<MODE>(ctp, vp);
+      to_operand<TRAJ_MODE_FP32>(ctp, vp);
       const f4 xd = eval<MODE>(evd, cx, cxb), yd = eval<MODE>(evd, cy, cyb);
       f4 th;
 #pragma unroll
       for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2_heading(yd[r], xd[r]) : 0.f;
       sth[w * WAVE + lane] = f4to(th);
-      W = contract<MODE>(ctp, th, W);
+      W = contract<TRAJ_MODE_FP32>(ctp, th, W);
     }
     return W;
   };
@@ -516,7 +519,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   // d), (alpha_a, d_a); no multiplier is updated here
   auto start = [&](bool cold_start) {
     const f4 W = heading_sweep();
-    if (cold_start) cp = apply_psi<MODE>(psi_ops(), P.c0p, rho * W + lp);
+    if (cold_start) cp = apply_psi(psi_ops(), P.c0p, rho * W + lp);
     projection_sweep(ux, uy, E);
   };
   auto iteration = [&]() {
@@ -525,7 +528,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     cy = apply_xy(xy_ops(1), c0d(1), cy, rho * uy + ly);
     // heading step (eq. 13 through eq. 20)
     const f4 W = heading_sweep();
-    cp = apply_psi<MODE>(psi_ops(), P.c0p, rho * W + lp);
+    cp = apply_psi(psi_ops(), P.c0p, rho * W + lp);
     // v, (alpha, d), (alpha_a, d_a), then the multipliers (eqs. 23, 24)
     projection_sweep(ux, uy, E);
     lx = lx + rho * ux;

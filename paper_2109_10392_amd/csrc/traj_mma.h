@@ -120,19 +120,15 @@ __device__ __forceinline__ f4 contract(const Operand<MODE>& a, const f4& s, f4 a
 //
 // The x/y step's constant operators are FP64 in both forms: they act on
 // coefficients of hundreds of metres, and their rounding is integrated by the
-// multipliers (eqs. 23, 24) over the iterations.
+// multipliers (eqs. 23, 24) over the iterations. The heading operator (eq. 20) is
+// FP32 in both forms: its entries reach ~70 and its row sums ~200 while its
+// products cancel to angles of tenths of a radian, so a split-BF16 product (about
+// 16 significant bits) would leave errors of ~1e-3 rad in the coefficients.
 struct XYOps {
   double mg[4], m[4];  // rows permuted for the f64 output layout
 };
-template <int MODE>
-struct PsiOps;
-template <>
-struct PsiOps<TRAJ_MODE_FP32> {
+struct PsiOps {
   float mp[4];
-};
-template <>
-struct PsiOps<TRAJ_MODE_BF16X3> {
-  bf8 mp[2];
 };
 
 __device__ __forceinline__ void load_xy_ops(XYOps& O, const double* __restrict__ T64, int axis, int j, int q) {
@@ -149,19 +145,11 @@ __device__ __forceinline__ void load_xy_ops(XYOps& O, const double* __restrict__
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ void load_psi_ops(PsiOps<MODE>& O, const float* __restrict__ T, int n, int j, int q) {
-  float mp[4];
+__device__ __forceinline__ void load_psi_ops(PsiOps& O, const float* __restrict__ T, int n, int j, int q) {
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int k = 4 * q + kk;
-    mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
-  }
-  if constexpr (MODE == TRAJ_MODE_FP32) {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) O.mp[kk] = mp[kk];
-  } else {
-    split_a(mp, O.mp[0], O.mp[1]);
+    O.mp[kk] = (j < NC && k < NC) ? T[tab_square(n, SQ_MP) + j * NC + k] : 0.f;
   }
 }
 
@@ -178,17 +166,10 @@ __device__ __forceinline__ f4 apply_xy(const XYOps& O, const d4& c0d, const f4& 
   return out;
 }
 
-template <int MODE>
-__device__ __forceinline__ f4 apply_psi(const PsiOps<MODE>& O, const f4& c0p, const f4& r) {
+__device__ __forceinline__ f4 apply_psi(const PsiOps& O, const f4& c0p, const f4& r) {
   f4 acc = c0p;
-  if constexpr (MODE == TRAJ_MODE_FP32) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mma32(O.mp[kk], r[kk], acc);
-  } else {
-    const bf8 rb = split_b(r);
-    acc = mmabf(O.mp[0], rb, acc);
-    acc = mmabf(O.mp[1], rb, acc);
-  }
+  for (int kk = 0; kk < 4; ++kk) acc = mma32(O.mp[kk], r[kk], acc);
   return acc;
 }
 
