@@ -167,7 +167,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* _
 
 struct GConsts {
   int n, m, nt;
-  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2, dt;
+  float rho, a, b, inv_a, inv_b, a2, b2, vmin, vmax, amax, amax2, dt, inv_tf;
 };
 
 template <int MODE>
@@ -334,6 +334,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   K.m = sd.m;
   K.nt = n_tiles(sd.n);
   K.dt = sd.t_f / (float)(sd.n - 1);
+  K.inv_tf = 1.f / sd.t_f;
   K.rho = A.k.rho;
   K.a = A.k.a;
   K.b = A.k.b;
@@ -416,11 +417,37 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     if constexpr (MODE == TRAJ_MODE_BF16X3) return split_b(v);
     else return bf8{};
   };
+  // positions: split relative to the end-to-end line, which is added back after
+  // each evaluation (value, first derivative; the second derivative has none)
+  auto split_pos = [&](const f4& v, Trend& L) -> bf8 {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+      L = trend_of(v, j, K.inv_tf);
+      return split_detrended(v, L, q);
+    } else {
+      L = Trend{0.f, 0.f, 0.f};
+      return bf8{};
+    }
+  };
+  auto plus_line = [&](f4 v, const Trend& L, const float (&t)[4]) {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += fmaf(L.v, t[r], L.c0);
+    }
+    return v;
+  };
+  auto plus_slope = [&](f4 v, const Trend& L) {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += L.v;
+    }
+    return v;
+  };
   // heading input: W = P^T theta, theta = atan2(y', x') at every sample
   // heading input: W = P^T theta, theta = atan2(y', x') at every sample; theta is
   // kept in this wave's LDS slice for the projection sweep that follows
   auto heading_sweep = [&]() -> f4 {
-    const bf8 cxb = split(cx), cyb = split(cy);
+    Trend Lx, Ly;
+    const bf8 cxb = split_pos(cx, Lx), cyb = split_pos(cy, Ly);
     f4 W = zero;
     float4 nd = pk[(0 * PACK_SLOTS + 1) * WAVE + lane], np = pk[(0 * PACK_SLOTS + 3) * WAVE + lane];
 #pragma unroll 1
@@ -436,7 +463,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
       Operand<TRAJ_MODE_FP32> ctp;
       to_operand<MODE>(evd, vd);
       to_operand<TRAJ_MODE_FP32>(ctp, vp);
-      const f4 xd = eval<MODE>(evd, cx, cxb), yd = eval<MODE>(evd, cy, cyb);
+      const f4 xd = plus_slope(eval<MODE>(evd, cx, cxb), Lx), yd = plus_slope(eval<MODE>(evd, cy, cyb), Ly);
       f4 th;
 #pragma unroll
       for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2_heading(yd[r], xd[r]) : 0.f;
@@ -450,7 +477,8 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   // per-sample values are contracted as soon as they exist.
   float racc[4];
   auto projection_sweep = [&](f4& ux, f4& uy, f4& E) {
-    const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
+    Trend Lx, Ly;
+    const bf8 cxb = split_pos(cx, Lx), cyb = split_pos(cy, Ly), cpb = split(cp);
     ux = zero;
     uy = zero;
     E = zero;
@@ -489,7 +517,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
           op[1] = nxt[1 * WAVE];
           op[4] = nxt[4 * WAVE];
         }
-        const f4 xd = eval<MODE>(ev, cx, cxb), yd = eval<MODE>(ev, cy, cyb);
+        const f4 xd = plus_slope(eval<MODE>(ev, cx, cxb), Lx), yd = plus_slope(eval<MODE>(ev, cy, cyb), Ly);
         to_operand<MODE>(ev, op[0]);
         const f4 psi = eval<MODE>(ev, cp, cpb);
         const f4 th = tof4(sth[w * WAVE + lane]);
@@ -501,7 +529,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
         E = contract<MODE>(ct, ep, E);
       }
       {  // obstacle rows
-        const f4 x = eval<MODE>(ev, cx, cxb), y = eval<MODE>(ev, cy, cyb);
+        const f4 x = plus_line(eval<MODE>(ev, cx, cxb), Lx, Tm), y = plus_line(eval<MODE>(ev, cy, cyb), Ly, Tm);
         if (more) {
           op[0] = nxt[0 * WAVE];
           op[3] = nxt[3 * WAVE];

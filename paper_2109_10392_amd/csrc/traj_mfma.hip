@@ -336,12 +336,42 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
     if constexpr (MODE == TRAJ_MODE_BF16X3) return split_b(v);
     else return bf8{};
   };
+  // positions: split relative to the end-to-end line, which is added back after
+  // each evaluation (value, first derivative; the second derivative has none)
+  const float inv_tf = 1.f / sd.t_f;
+  float tline[4];  // times of the lane's 4 samples
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tline[r] = (float)(TILE * w + 4 * q + r) * (sd.t_f / (float)(n - 1));
+  auto split_pos = [&](const f4& v, Trend& L) -> bf8 {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+      L = trend_of(v, j, inv_tf);
+      return split_detrended(v, L, q);
+    } else {
+      L = Trend{0.f, 0.f, 0.f};
+      return bf8{};
+    }
+  };
+  auto plus_line = [&](f4 v, const Trend& L) {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += fmaf(L.v, tline[r], L.c0);
+    }
+    return v;
+  };
+  auto plus_slope = [&](f4 v, const Trend& L) {
+    if constexpr (MODE == TRAJ_MODE_BF16X3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += L.v;
+    }
+    return v;
+  };
   // one pass of the per-sample blocks at the current coefficients; returns u~
   // (summed over the workgroup) and the lane's residual partials
   auto heading = [&](f4& xd, f4& yd, f4& th, f4& W_, f4& E_) {
-    const bf8 cxb = split(cx), cyb = split(cy);
-    xd = evalO<MODE>(O, 1, cx, cxb);
-    yd = evalO<MODE>(O, 1, cy, cyb);
+    Trend Lx, Ly;
+    const bf8 cxb = split_pos(cx, Lx), cyb = split_pos(cy, Ly);
+    xd = plus_slope(evalO<MODE>(O, 1, cx, cxb), Lx);
+    yd = plus_slope(evalO<MODE>(O, 1, cy, cyb), Ly);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool tv = gv && (TILE * w + 4 * q + r) < n;
@@ -362,8 +392,9 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
     buf ^= 1;
   };
   auto project = [&](const f4& xd, const f4& yd, const f4& th) {
-    const bf8 cxb = split(cx), cyb = split(cy), cpb = split(cp);
-    const f4 x = evalO<MODE>(O, 0, cx, cxb), y = evalO<MODE>(O, 0, cy, cyb);
+    Trend Lx, Ly;
+    const bf8 cxb = split_pos(cx, Lx), cyb = split_pos(cy, Ly), cpb = split(cp);
+    const f4 x = plus_line(evalO<MODE>(O, 0, cx, cxb), Lx), y = plus_line(evalO<MODE>(O, 0, cy, cyb), Ly);
     const f4 xdd = evalO<MODE>(O, 2, cx, cxb), ydd = evalO<MODE>(O, 2, cy, cyb);
     const f4 psi = evalO<MODE>(O, 0, cp, cpb);
     SampleOut so;

@@ -173,6 +173,34 @@ __device__ __forceinline__ f4 apply_psi(const PsiOps& O, const f4& c0p, const f4
   return acc;
 }
 
+// End-to-end line of a position coefficient vector (rows 4q + r of goal column j).
+// A Bernstein basis reproduces linear coefficients exactly (sum_k B_k = 1 and
+// sum_k (k/N) B_k = tau), so c_k = c0 + (cN - c0) k/N evaluates to c0 + v t with
+// v = (cN - c0) / t_f, its derivative to v and its second derivative to 0. The
+// split-BF16 form evaluates the coefficients relative to this line and adds the
+// line back in FP32: the split (about 16 significant bits) then carries the
+// deviation from uniform motion, metres, instead of positions of hundreds of metres.
+struct Trend {
+  float c0, d, v;  // first coefficient, last minus first, slope in time
+};
+static_assert(NC == 11, "the last coefficient row N = 10 is register 2 of row group 2");
+
+__device__ __forceinline__ Trend trend_of(const f4& c, int j, float inv_tf) {
+  Trend L;
+  L.c0 = __shfl(c[0], j);                 // row 0: row group 0, register 0
+  const float cN = __shfl(c[2], j + 32);  // row 10: row group 2, register 2
+  L.d = cN - L.c0;
+  L.v = L.d * inv_tf;
+  return L;
+}
+
+__device__ __forceinline__ bf8 split_detrended(const f4& c, const Trend& L, int q) {
+  f4 e;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) e[r] = c[r] - fmaf(L.d, (float)(4 * q + r) * (1.f / (NC - 1)), L.c0);
+  return split_b(e);
+}
+
 __device__ __forceinline__ float4 f4to(const f4& v) { return make_float4(v[0], v[1], v[2], v[3]); }
 __device__ __forceinline__ f4 tof4(const float4& v) {
   f4 r = {v.x, v.y, v.z, v.w};

@@ -1,7 +1,7 @@
 """Group kernel (one wavefront per goal group, cost-sorted work list): parity
 with the oracle, invariances, the persistent schedule and hipGraph replay.
 
-FP32 runs the 1e-4 gate of the other kernels. Goal groups are independent MFMA
+FP32 runs the 1e-4 gate of the other kernels, the split-BF16 form its own 5e-4. Goal groups are independent MFMA
 columns, so the group size and the schedule (list order or persistent claiming)
 must not change any bit of the result when no tolerance stop is used.
 """
@@ -14,8 +14,8 @@ from tests.conftest import report_path
 
 from oracle import traj_oracle as O
 from paper_2109_10392_amd import scenes as S
-from tests.test_gpu_parity import (PARAMS, TOL, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
-                                   undetermined_goals)
+from tests.test_gpu_parity import (PARAMS, TOL, TOL_BF16X3, check_gate, coef_err, gpu_solve, oracle_scene,
+                                   ragged_batch, undetermined_goals)
 
 pytestmark = pytest.mark.gpu
 
@@ -194,7 +194,8 @@ def test_group_hipgraph_replay_matches_eager(T):
 
 
 def test_bf16x3_group_precision_report(T):
-    """Split-BF16 form on the group kernel: error vs FP64 reported per scene."""
+    """Split-BF16 form on the group kernel: error vs FP64 reported per scene and
+    held to the split form's gate."""
     rows = []
     for seed in range(10):
         batch = S.workload_small(seed)
@@ -218,6 +219,7 @@ def test_bf16x3_group_precision_report(T):
     with open(report_path("bf16x3_group_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9
+    assert max(r["coef_err_max"] for r in rows) <= TOL_BF16X3
 
 
 def test_uneven_full_batch_sampled(T):

@@ -1,11 +1,11 @@
 """Matrix-core kernel: FP32 parity with the oracle, invariances, and the split-BF16 precision report.
 
 The FP32 form runs the same gate as the wave kernel (1e-4 per goal and axis,
-bifurcating goals checked for validity). The BF16x3 form (every contraction
-and apply on split-BF16 MFMA, FP32 accumulation) has no hard accuracy gate:
-its coefficient and residual errors against the FP64 oracle are reported per
-scene, and the test checks that they are finite and that the best goal is the
-oracle's (or a near-tie).
+bifurcating goals checked for validity). The split-BF16 form (basis evaluations
+and contractions on split-BF16 MFMA with FP32 accumulation, x/y applies in FP64,
+the heading path in FP32) is held to 5e-4 on the same measure; its coefficient
+and residual errors against the FP64 oracle are reported per scene, and the test
+checks that they are finite and that the best goal is the oracle's (or a near-tie).
 """
 import json
 
@@ -16,7 +16,7 @@ from tests.conftest import report_path
 
 from oracle import traj_oracle as O
 from paper_2109_10392_amd import scenes as S
-from tests.test_gpu_parity import (TOL, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
+from tests.test_gpu_parity import (TOL, TOL_BF16X3, check_gate, coef_err, gpu_solve, oracle_scene, ragged_batch,
                                    undetermined_goals)
 
 pytestmark = pytest.mark.gpu
@@ -98,7 +98,8 @@ def test_mfma_tolerance_stop(T):
 
 
 def test_bf16x3_precision_report(T):
-    """Precision form on the 11-goal scenes: error vs FP64 reported per scene."""
+    """Precision form on the 11-goal scenes: error vs FP64 reported per scene and
+    held to the split form's gate."""
     rows = []
     for seed in range(10):
         batch = S.workload_small(seed)
@@ -122,3 +123,4 @@ def test_bf16x3_precision_report(T):
     with open(report_path("bf16x3_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9
+    assert max(r["coef_err_max"] for r in rows) <= TOL_BF16X3
