@@ -38,8 +38,8 @@ MEASURED_TRAFFIC = {
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "62cdb7c4c04577ecd179193070743a77252e509e81624bfbc4851336f55344f2",
-               "bytes_per_launch": int((85788.3 * 2.0 + 277103.8) * 1024),
+               "sha256": "0cdbd01ac2626028e97895c0f714c7aa9aa2a2a51e57f9c22dc22218c466d28d",
+               "bytes_per_launch": int((84665.3 * 2.0 + 278661.1) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
