@@ -199,7 +199,7 @@ def run_mpc(args):
     from paper_2109_10392_amd import mpc
     torch.cuda.set_device(0)
     cl = mpc.ClosedLoop(range(args.episodes), iters=args.iters, warm=args.warm, clear_min=args.clear_min,
-                        scenario=args.scenario)
+                        scenario=args.scenario, precision=args.precision)
     for _ in range(args.warmup):
         cl.cycle()
     torch.cuda.synchronize()
@@ -214,12 +214,15 @@ def run_mpc(args):
     return {
         "metric": "closed-loop episode-cycles/s", "value": args.episodes / (ms / 1e3), "unit": "episode-cycles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
         "config": {"workload": f"closed loop: {args.episodes} episodes, 4 lanes, 10 IDM vehicles each, 256 goals "
                                f"per plan, replanning every sample interval (0.101 s), at most {args.iters} "
                                f"iterations per plan (stop at residual 1e-3), start: {args.warm}, "
-                               f"collision post-check at {args.clear_min}, scenario: {args.scenario}",
+                               f"collision post-check at {args.clear_min}, scenario: {args.scenario}, "
+                               f"precision: {args.precision}",
                    "episodes": args.episodes, "warm": args.warm, "clear_min": args.clear_min,
+                   "precision": args.precision,
                    "scenario": args.scenario},
         "closed_loop": m,
     }
