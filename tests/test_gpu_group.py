@@ -1,8 +1,8 @@
 """Group kernel (one wavefront per goal group, cost-sorted work list): parity
 with the oracle, invariances, the persistent schedule and hipGraph replay.
 
-FP32 runs the 1e-4 gate of the other kernels, the split-BF16 form its own 5e-4. Goal groups are independent MFMA
-columns, so the group size and the schedule (list order or persistent claiming)
+FP32 runs the 1e-4 gate of the other kernels, the split-BF16 form its own 1e-3.
+Goal groups are independent MFMA columns, so the group size and the schedule (list order or persistent claiming)
 must not change any bit of the result when no tolerance stop is used.
 """
 import json
@@ -222,21 +222,26 @@ def test_bf16x3_group_precision_report(T):
     assert max(r["coef_err_max"] for r in rows) <= TOL_BF16X3
 
 
-def test_uneven_full_batch_sampled(T):
+_UNEVEN_ORACLE = {}  # scene index -> (prob, oracle state) of its sampled goals
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_uneven_full_batch_sampled(T, precision):
     """The uneven workload at its full size (512 scenes, 118,830 goals, T in {50,
     100, 150}, 4-64 obstacles) in the launch configuration its benchmark times
-    (group kernel, 16 goals, persistent, FP32, 100 iterations): the first, middle
-    and last goal of twelve scenes spanning the shapes against the oracle, and the
-    ranking of those scenes against the oracle's meta-cost of the same
-    coefficients."""
+    (group kernel, 16 goals, persistent, 100 iterations), in FP32 and in the
+    split-BF16 form: the first, middle and last goal of twelve scenes spanning the
+    shapes against the oracle (gates 1e-4 and 1e-3), and the ranking of those
+    scenes against the oracle's meta-cost of the same coefficients."""
     import torch
+    tol = TOL if precision == "fp32" else TOL_BF16X3
     batch = S.workload_uneven(0)
     assert batch.n_scenes == 512 and batch.n_goals == 118830
     solver = T.Solver(PARAMS, batch.shapes())
     solver.set_tile("group", 16, True)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
-    solver.solve(db, st, 100)
+    solver.solve(db, st, 100, precision=precision)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
     cost = torch.zeros(batch.n_goals, device="cuda")
     best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
@@ -257,10 +262,12 @@ def test_uneven_full_batch_sampled(T):
         sc = batch.scenes[i]
         G = sc.goals.shape[0]
         goals = sorted({0, G // 2, G - 1})
-        prob, ref = oracle_scene(sc, 100, goals=goals)
+        if i not in _UNEVEN_ORACLE:
+            _UNEVEN_ORACLE[i] = oracle_scene(sc, 100, goals=goals)
+        prob, ref = _UNEVEN_ORACLE[i]
         sl = [off[i] + g for g in goals]
         print(f"scene {i}: T={sc.n_time}, m={sc.obs.shape[0]}, goals={G}")
-        check_gate(c[:, :, sl], prob, sc, ref, 100, goals=goals, max_undetermined=0.67)
+        check_gate(c[:, :, sl], prob, sc, ref, 100, goals=goals, max_undetermined=0.67, tol=tol)
         # ranking of the scene's computed trajectories
         sls = slice(off[i], off[i + 1])
         rc = O.meta_cost(prob, c[0][:, sls].astype(np.float64), c[1][:, sls].astype(np.float64),

@@ -3,7 +3,7 @@
 The FP32 form runs the same gate as the wave kernel (1e-4 per goal and axis,
 bifurcating goals checked for validity). The split-BF16 form (basis evaluations
 and contractions on split-BF16 MFMA with FP32 accumulation, x/y applies in FP64,
-the heading path in FP32) is held to 5e-4 on the same measure; its coefficient
+the heading path in FP32) is held to 1e-3 on the same measure; its coefficient
 and residual errors against the FP64 oracle are reported per scene, and the test
 checks that they are finite and that the best goal is the oracle's (or a near-tie).
 """
@@ -41,13 +41,22 @@ def test_mfma_fp32_small_parity(T, seed):
     check_gate(out["c"], prob, batch.scenes[0], st, 100)
 
 
-def test_mfma_fp32_dense_sampled(T):
+_DENSE_ORACLE = {}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mfma_dense_sampled(T, precision):
+    """Dense scene (1024 goals, 50 obstacles), sampled goals against the oracle:
+    FP32 at 1e-4, the split-BF16 form at 1e-3."""
     batch = S.workload_dense(0)
-    out = gpu_solve(T, batch, 100, kernel="mfma")
+    out = gpu_solve(T, batch, 100, kernel="mfma", precision=precision)
     sample = [0, 1, 2, 3, 4, 5, 63, 64, 255, 256, 511, 700, 1000, 1021, 1022, 1023]
-    prob, st = oracle_scene(batch.scenes[0], 100, goals=sample)
-    print("dense, sampled goals:")
-    check_gate(out["c"][:, :, sample], prob, batch.scenes[0], st, 100, goals=sample)
+    if "ref" not in _DENSE_ORACLE:
+        _DENSE_ORACLE["ref"] = oracle_scene(batch.scenes[0], 100, goals=sample)
+    prob, st = _DENSE_ORACLE["ref"]
+    print(f"dense, sampled goals ({precision}):")
+    check_gate(out["c"][:, :, sample], prob, batch.scenes[0], st, 100, goals=sample,
+               tol=TOL if precision == "fp32" else TOL_BF16X3)
     assert np.all(np.isfinite(out["c"]))
 
 

@@ -19,10 +19,11 @@ pytestmark = pytest.mark.gpu
 
 PARAMS = S.DEFAULT_PARAMS
 TOL = 1e-4
-# The split-BF16 form keeps about 16 significant bits in its split products (the
-# x/y applies in FP64, the heading path in FP32, positions split relative to their
-# end-to-end line); its gate on the same measure, for determined goals, is 5e-4.
-TOL_BF16X3 = 5e-4
+# The split-BF16 form keeps about 16 of FP32's 24 significant bits in its split
+# evaluations and contractions (the x/y applies stay FP64, the heading path FP32,
+# positions are split relative to their end-to-end line); its gate on the same
+# measure, for determined goals, is a decade above FP32's.
+TOL_BF16X3 = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -76,12 +77,12 @@ def undetermined_goals(prob, sc, st, iters, goals=None, shift=1e-6, thresh=1e-5)
     return coef_err(c64, st2).max(0) > thresh
 
 
-def check_gate(out_c, prob, sc, st, iters, goals=None, max_undetermined=0.35):
+def check_gate(out_c, prob, sc, st, iters, goals=None, max_undetermined=0.35, tol=TOL):
     err = coef_err(out_c, st).max(0)
     und = undetermined_goals(prob, sc, st, iters, goals)
     print(f"  gated goals: {np.count_nonzero(~und)}/{und.size}, max rel err {err[~und].max() if (~und).any() else 0:.2e}; "
           f"undetermined (bifurcating) goals {np.flatnonzero(und).tolist()} err {np.array2string(err[und], precision=1)}")
-    assert np.all(err[~und] <= TOL), err
+    assert np.all(err[~und] <= tol), err
     assert np.count_nonzero(und) <= max_undetermined * und.size
     # undetermined goals: still a valid iterate (finite, boundary rows of eq. 8b met)
     assert np.all(np.isfinite(out_c))
