@@ -152,7 +152,12 @@ int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes
  *   concurrently.
  *   iters: 0 <= iters <= 100000. n_goals == 0 is a no-op.
  * Shape mismatches found on the device (unknown shape id, wrong obstacle count)
- * set that scene's residuals to NaN; nothing aborts.
+ * set that scene's residuals to NaN; nothing aborts. Input values that are not
+ * finite are found on the device too: a scene whose ego state or any obstacle
+ * state is not finite has every goal marked, a goal whose target is not finite
+ * is marked alone. A marked goal's c, lam and residuals become NaN and its
+ * iteration count 0 (traj_score gives it a NaN cost and never picks it); the
+ * other goals are solved as if the marked ones were absent.
  * Errors: TRAJ_E_INVAL (null pointers, negative sizes), TRAJ_E_HIP.
  */
 int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, int iters, float tol,
@@ -239,8 +244,9 @@ int traj_get_tile(void *handle, traj_tile *tile);
  * traj_work_ints -- entries of the int32 device scratch (traj_state.work) that a
  * group-kernel solve of a batch with n_scenes scenes and n_goals goals needs with
  * the handle's current group size: 4 + 2 (ceil(n_goals / group) + n_scenes) +
- * n_goals (claim counter, the cost-sorted list of goal groups, the goal order of
- * every scene). The wave and MFMA kernels do not use the scratch. Host-only.
+ * n_goals + n_scenes (claim counter, the cost-sorted list of goal groups, the goal
+ * order of every scene, the goals of each scene that are solved). The wave and
+ * MFMA kernels do not use the scratch. Host-only.
  * Errors: TRAJ_E_INVAL (NULL handle or out, negative sizes).
  */
 int traj_work_ints(void *handle, int n_scenes, int n_goals, int64_t *out);

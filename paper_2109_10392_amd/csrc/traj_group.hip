@@ -46,6 +46,7 @@ struct GroupArgs {
   int32_t* header;   // [0] claim counter, [1] groups listed
   int2* items;        // (scene, first position in the scene's goal order) per group, decreasing cost
   int32_t* perm;      // [n_goals]: goal index at each position of its scene's order
+  int32_t* nvalid;    // [n_scenes]: goals of the scene that are solved (the first of its order)
   int capacity;       // entries of items
   int G;              // goals per group, 1..16
   int persistent;
@@ -74,9 +75,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int b = tid; b < COST_BUCKETS; b += LIST_THREADS) hist[b] = 0;
   __syncthreads();
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
-    int g0, g1;
-    scene_goals(A, s, g0, g1);
-    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (g1 - g0 + L.G - 1) / L.G;
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + L.G - 1) / L.G;
     if (cnt > 0) atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
   }
   __syncthreads();
@@ -106,7 +105,7 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
     int g0, g1;
     scene_goals(A, s, g0, g1);
-    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (g1 - g0 + L.G - 1) / L.G;
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + L.G - 1) / L.G;
     if (cnt <= 0) continue;
     int pos = atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
     for (int i = 0; i < cnt && pos < L.capacity; ++i, ++pos)
@@ -129,20 +128,43 @@ __device__ __forceinline__ unsigned sort_key(float v) {
 // segment). One workgroup per scene, bitonic sort of (key, index) pairs in LDS.
 // Any permutation of a scene's goal range gives the same results; the order only
 // makes the goals of a group close together.
-__global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* __restrict__ perm) {
+//
+// Inputs a solve cannot use are found here: a scene whose ego state (the
+// boundary values of eq. 8b) or any obstacle state is not finite has every goal
+// marked, a goal whose target is not finite is marked alone. The solved goals
+// take the first nvalid positions of the scene's order and the marked ones the
+// rest; a marked goal's outputs are written here (NaN coefficients, multipliers
+// and residuals, zero iterations) and the solve never reaches it.
+__global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* __restrict__ perm,
+                                                         int32_t* __restrict__ nvalid) {
   __shared__ unsigned long long key[ORDER_THREADS];
   __shared__ int idx[ORDER_THREADS];
+  constexpr unsigned long long MARKED = 0xFFFFFFFF00000000ull;  // after every finite (y_f, x_f) key
   const int s = blockIdx.x;
   const int t = threadIdx.x;
   int g0, g1;
   scene_goals(A, s, g0, g1);
+  int bad = t < 8 && !__builtin_isfinite(A.ego[8 * s + t]);
+  // the obstacles are read only where the solve would read them (a known shape
+  // with the scene's obstacle count; otherwise the solve marks the scene itself)
+  const int sid = A.shape_id[s];
+  const int o0 = A.obs_off[s], m_scene = A.obs_off[s + 1] - o0;
+  if (sid >= 0 && sid < A.n_shapes && A.shapes[sid].m == m_scene && m_scene <= MAX_OBS)
+    for (int j = t; j < m_scene; j += ORDER_THREADS) bad |= !all_finite(A.obs + 4 * (o0 + j), 4);
+  const bool scene_marked = __syncthreads_or(bad) != 0;
+  auto solved = [&](int i) { return i < g1 && !scene_marked && all_finite(A.goal + 2 * i, 2); };
+  int total = 0;
+  for (int seg = g0; seg < g1; seg += ORDER_THREADS) total += __syncthreads_count(solved(seg + t));
+  if (t == 0) nvalid[s] = total;
+  int done_valid = 0, done_marked = 0;
   for (int seg = g0; seg < g1; seg += ORDER_THREADS) {
     const int cnt = min(ORDER_THREADS, g1 - seg);
     const int i = seg + t;
-    key[t] = t < cnt ? (((unsigned long long)sort_key(A.goal[2 * i + 1]) << 32) | sort_key(A.goal[2 * i]))
-                     : ~0ull;
+    const bool valid = t < cnt && solved(i);
+    key[t] = valid ? (((unsigned long long)sort_key(A.goal[2 * i + 1]) << 32) | sort_key(A.goal[2 * i]))
+                   : (t < cnt ? MARKED : ~0ull);
     idx[t] = t;
-    __syncthreads();
+    const int seg_valid = __syncthreads_count(valid);
     for (int k = 2; k <= ORDER_THREADS; k <<= 1) {
       for (int jx = k >> 1; jx > 0; jx >>= 1) {
         const int l = t ^ jx;
@@ -160,7 +182,13 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* _
         __syncthreads();
       }
     }
-    if (t < cnt) perm[seg + t] = seg + idx[t];
+    if (t < cnt) {
+      const int pos = t < seg_valid ? g0 + done_valid + t : g0 + total + done_marked + (t - seg_valid);
+      perm[pos] = seg + idx[t];
+    }
+    if (t < cnt && !valid) write_marked_goal(A, i, 0, 1);
+    done_valid += seg_valid;
+    done_marked += cnt - seg_valid;
     __syncthreads();
   }
 }
@@ -305,12 +333,12 @@ __device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* _
 
 template <int MODE>
 __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm, int G, int scene, int pos0,
-                            int lane, float4* sobs, float4* sth, double* sc0) {
+                            int n_solved, int lane, float4* sobs, float4* sth, double* sc0) {
   const int j = lane & 15, q = lane >> 4;
   const int NG = A.n_goals;
   int s0, s1;
   scene_goals(A, scene, s0, s1);
-  const int gcount = min(G, s1 - pos0);
+  const int gcount = min(G, min(s1, s0 + n_solved) - pos0);
   if (gcount <= 0) return;
   const bool gv = j < gcount;
   const int g = perm[pos0 + (gv ? j : 0)];
@@ -660,7 +688,7 @@ __global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A,
   // every wavefront leaves once the list is exhausted: the counter only grows
   while (idx < n_items) {
     const int2 it = L.items[idx];
-    solve_group<MODE>(A, L.perm, L.G, it.x, it.y, lane, sobs[wv], sth[wv], sc0[wv]);
+    solve_group<MODE>(A, L.perm, L.G, it.x, it.y, L.nvalid[it.x], lane, sobs[wv], sth[wv], sc0[wv]);
     idx = L.persistent ? claim(L.header) : n_items;
   }
 }
@@ -676,8 +704,8 @@ int64_t group_capacity(int n_scenes, int n_goals, int G) {
 }  // namespace
 
 int64_t group_work_ints(int n_scenes, int n_goals, int G) {
-  // header (4) | (scene, first position) per group | goal order [n_goals]
-  return 4 + 2 * group_capacity(n_scenes, n_goals, G) + (int64_t)n_goals;
+  // header (4) | (scene, first position) per group | goal order [n_goals] | solved goals per scene
+  return 4 + 2 * group_capacity(n_scenes, n_goals, G) + (int64_t)n_goals + (int64_t)n_scenes;
 }
 
 hipError_t group_blocks_per_cu(int mode, int* blocks) {
@@ -696,12 +724,13 @@ hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persiste
   L.header = work;
   L.items = reinterpret_cast<int2*>(work + 4);
   L.perm = work + 4 + 2 * cap64;
+  L.nvalid = L.perm + a.n_goals;
   L.capacity = (int)cap64;
   L.G = G;
   L.persistent = persistent ? 1 : 0;
   hipError_t e;
   if (!reuse_order) {
-    hipLaunchKernelGGL(k_order, dim3(a.n_scenes), dim3(ORDER_THREADS), 0, stream, a, L.perm);
+    hipLaunchKernelGGL(k_order, dim3(a.n_scenes), dim3(ORDER_THREADS), 0, stream, a, L.perm, L.nvalid);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -101,6 +101,38 @@ struct SolveArgs {
   SolverConst k;
 };
 
+// Inputs a solve cannot use: a scene whose ego state (the boundary values of
+// eq. 8b) or any obstacle state is not finite marks every goal of the scene; a
+// goal whose target is not finite marks that goal. A marked goal's coefficients,
+// multipliers and residuals become NaN and its iteration count 0 (so scoring
+// never picks it); the other goals are solved as usual.
+// The check reads through an offset the compiler cannot see through (an empty asm
+// statement), so its loads are not merged with the solve's own later reads of the
+// same values, which would keep those live across the whole solve.
+__device__ __forceinline__ bool all_finite(const float* v, int count) {
+  int opaque = 0;
+  asm volatile("" : "+s"(opaque));
+  v += opaque;
+  bool ok = true;
+  for (int i = 0; i < count; ++i) ok = ok && __builtin_isfinite(v[i]);
+  return ok;
+}
+
+// the outputs of a marked goal, written by `parts` lanes of which this is `part`
+__device__ __forceinline__ void write_marked_goal(const SolveArgs& A, int g, int part, int parts) {
+  const float nan = __builtin_nanf("");
+  const int NG = A.n_goals;
+  for (int e = part; e < 3 * NC; e += parts) {
+    A.c[e * NG + g] = nan;
+    A.lam[e * NG + g] = nan;
+  }
+  if (part == 0) {
+    if (A.resid != nullptr)
+      for (int k = 0; k < 4; ++k) A.resid[k * NG + g] = nan;
+    if (A.iters_out != nullptr) A.iters_out[g] = 0;
+  }
+}
+
 struct ScoreArgs {
   const int32_t* goal_off;
   const int32_t* shape_id;

@@ -242,6 +242,8 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   float2* xi = reinterpret_cast<float2*>(smem);
   float4* box = reinterpret_cast<float4*>(smem + sizeof(float2) * (size_t)m * K.n_pad);
   float4* ex = box + (size_t)Wl * m;
+  int obs_marked = 0;  // a non-finite obstacle state seen by this thread
+  for (int jo = tid; jo < m; jo += blockDim.x) obs_marked |= !all_finite(A.obs + 4 * (o0 + jo), 4);
   {
     const float dt = sd.t_f / (float)(n - 1);
     for (int e = tid; e < m * K.n_pad; e += blockDim.x) {
@@ -265,20 +267,27 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
       box[e] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
     }
   }
-  __syncthreads();
+  if (__syncthreads_or(obs_marked) != 0 || !all_finite(A.ego + 8 * scene, 8)) {  // workgroup-uniform
+    if (j < gcount) write_marked_goal(A, g0 + j, tid / 16, (int)blockDim.x / 16);
+    return;
+  }
 
   const float* T = A.tables + sd.table_off;
   const double* T64 = A.tables64 + sd.table64_off;
   Ops<MODE> O;
   load_ops<MODE>(O, T, T64, n, w, j, q);
-  const bool gv = j < gcount;
-  const int g = g0 + (gv ? j : 0);
+  const bool gin = j < gcount;  // the lane's column holds a goal
+  const int g = g0 + (gin ? j : 0);
+  // a goal with a non-finite target is marked here and carried as a padding
+  // column (on the ego's start position instead of its target), never stored
+  const bool gv = gin && all_finite(A.goal + 2 * g, 2);
+  if (w == 0 && gin && !gv) write_marked_goal(A, g, q, 4);
   const int NG = A.n_goals;
   const float rho = K.rho;
 
   // boundary values (eq. 8b) and the particular parts M_b b of each step (rows 4q + r)
   const float* e = A.ego + 8 * scene;
-  const float* gl = A.goal + 2 * g;
+  const float* gl = gv ? A.goal + 2 * g : e;
   const float bx[NX] = {e[0], e[2], e[4], gl[0]};
   const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
   const float bp[NP] = {e[6], e[7], 0.f, 0.f};

@@ -474,8 +474,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   const int n = sd.n, m = sd.m;
   const float dt = sd.t_f / (float)(n - 1);
   const float inv_a = 1.f / A.k.a, inv_b = 1.f / A.k.b;
+  int obs_marked = 0;  // a non-finite obstacle state seen by this thread
   for (int j = tid; j < m; j += THREADS) {
     const float* o = A.obs + 4 * (o0 + j);
+    obs_marked |= !all_finite(o, 4);
     sobs[j] = make_float4(o[0] * inv_a, o[1] * inv_b, o[2] * inv_a, o[3] * inv_b);
   }
   // Boxes per slot row (16 samples): the scaled prediction fma(v', t, p') is
@@ -500,8 +502,12 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
     apply64[2 * NC * NC + e] = T64[T64_MGY + e];
     apply64[3 * NC * NC + e] = T64[T64_MY + e];
   }
-  __syncthreads();
+  const bool scene_marked = __syncthreads_or(obs_marked) != 0 || !all_finite(A.ego + 8 * scene, 8);
   if (g >= g1) return;  // only with one wave per goal (a two-wave workgroup always has its goal)
+  if (scene_marked || !all_finite(A.goal + 2 * g, 2)) {  // uniform over the goal's waves
+    if (writer) write_marked_goal(A, g, tid & 63, WAVE);
+    return;
+  }
   solve_goal<S, WPG>(A, sd, A.tables + sd.table_off, sobs, box, apply64, ex, scene, g);
 }
 

@@ -122,7 +122,7 @@ def test_group_needs_a_work_buffer_of_sufficient_size(T):
     solver = T.Solver(PARAMS, batch.shapes())
     solver.set_tile("group", 4)
     need = solver.work_ints(batch.n_scenes, batch.n_goals)
-    assert need == 4 + 2 * ((batch.n_goals + 3) // 4 + batch.n_scenes) + batch.n_goals
+    assert need == 4 + 2 * ((batch.n_goals + 3) // 4 + batch.n_scenes) + batch.n_goals + batch.n_scenes
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
     st.work = torch.zeros(need - 1, dtype=torch.int32, device="cuda")
