@@ -33,13 +33,13 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "3a2e86cbcac7393f2ba0d5e6ff0bf0a9c14e4ca2da26e9323379d5bde3966a9e",
-              "bytes_per_launch": int((279.0 * 2.0 + 2272.0) * 1024),
+              "sha256": "6217d8b27f38d60cfafb321b9383f126cbcb149aa5900385add25558415ea4c6",
+              "bytes_per_launch": int((279.5 * 2.0 + 2272.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "4bf36e914b843a092b532f387568753bffe570c5d58589f0e8246a872b510fc0",
-               "bytes_per_launch": int((90597.7 * 2.0 + 277783.2) * 1024),
+               "sha256": "c383e081dd089b39b24dc941542c29e2f5c71b68dd0b5519c4cf46f297acca3b",
+               "bytes_per_launch": int((77001.5 * 2.0 + 278252.4) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 

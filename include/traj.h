@@ -151,8 +151,9 @@ int traj_setup(const traj_params *params, const traj_shape *shapes, int n_shapes
  *   (TRAJ_E_INVAL otherwise). Two solves that share a work buffer must not run
  *   concurrently.
  *   iters: 0 <= iters <= 100000. n_goals == 0 is a no-op.
- * Shape mismatches found on the device (unknown shape id, wrong obstacle count)
- * set that scene's residuals to NaN; nothing aborts. Input values that are not
+ * Shape mismatches found on the device (unknown shape id, wrong obstacle count,
+ * an obstacle range starting before the array) set that scene's residuals to
+ * NaN and its obstacles are not read; nothing aborts. Input values that are not
  * finite are found on the device too: a scene whose ego state or any obstacle
  * state is not finite has every goal marked, a goal whose target is not finite
  * is marked alone. A marked goal's c, lam and residuals become NaN and its

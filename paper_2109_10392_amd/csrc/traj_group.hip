@@ -149,7 +149,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_order(SolveArgs A, int32_t* _
   // with the scene's obstacle count; otherwise the solve marks the scene itself)
   const int sid = A.shape_id[s];
   const int o0 = A.obs_off[s], m_scene = A.obs_off[s + 1] - o0;
-  if (sid >= 0 && sid < A.n_shapes && A.shapes[sid].m == m_scene && m_scene <= MAX_OBS)
+  if (sid >= 0 && sid < A.n_shapes && obstacles_ok(o0, m_scene, A.shapes[sid].m))
     for (int j = t; j < m_scene; j += ORDER_THREADS) bad |= !all_finite(A.obs + 4 * (o0 + j), 4);
   const bool scene_marked = __syncthreads_or(bad) != 0;
   auto solved = [&](int i) { return i < g1 && !scene_marked && all_finite(A.goal + 2 * i, 2); };
@@ -348,7 +348,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   bool bad = sid < 0 || sid >= A.n_shapes;
   ShapeDesc sd = {};
   if (!bad) sd = A.shapes[sid];
-  bad = bad || m_scene != sd.m || sd.n < NC || sd.n > MAX_TIME;
+  bad = bad || !obstacles_ok(o0, m_scene, sd.m) || sd.n < NC || sd.n > MAX_TIME;
   if (bad) {
     if (gv && q == 0) {
       if (A.resid != nullptr)

@@ -101,6 +101,13 @@ struct SolveArgs {
   SolverConst k;
 };
 
+// A scene's obstacle range [obs_off[s], obs_off[s+1]) as the kernels read it: a
+// non-negative start and the obstacle count of the scene's shape (at most MAX_OBS).
+// Any other range is never read; the scene is marked like one of unknown shape.
+__device__ __forceinline__ bool obstacles_ok(int o0, int m_scene, int m_shape) {
+  return o0 >= 0 && m_scene == m_shape && m_scene >= 0 && m_scene <= MAX_OBS;
+}
+
 // Inputs a solve cannot use: a scene whose ego state (the boundary values of
 // eq. 8b) or any obstacle state is not finite marks every goal of the scene; a
 // goal whose target is not finite marks that goal. A marked goal's coefficients,

@@ -203,6 +203,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   if (scene < 0) return;
   if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
   const int g0 = sh[1];
+  if (g0 < 0) return;  // goal offsets out of contract: nothing to touch
   const int gcount = min(min(G, (int)A.goal_off[scene + 1] - g0), A.n_goals - g0);
   const int sid = A.shape_id[scene];
   const int o0 = A.obs_off[scene];
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   bool bad = sid < 0 || sid >= A.n_shapes;
   ShapeDesc sd = {};
   if (!bad) sd = A.shapes[sid];
-  bad = bad || m_scene != sd.m || sd.n < NC || (sd.n + TILE - 1) / TILE > Wl;
+  bad = bad || !obstacles_ok(o0, m_scene, sd.m) || sd.n < NC || (sd.n + TILE - 1) / TILE > Wl;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid >> 6;
   const int j = lane & 15, q = lane >> 4;
   if (bad) {

@@ -162,7 +162,7 @@ __global__ void k_features(const int32_t* __restrict__ obs_off, const float* __r
   const float* e = ego + 8 * s;
   const int o0 = obs_off[s], m = obs_off[s + 1] - o0;
   float v = 0.f;  // feature `lane` of the scene
-  if (m < 0 || m > 64) {
+  if (o0 < 0 || m < 0 || m > 64) {
     v = __builtin_nanf("");
   } else {
     if (lane == 0) v = e[2] * (1.f / 30.f);

@@ -80,6 +80,10 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
   const float yrl = (A.kind == 1 && A.y_rl != nullptr) ? A.y_rl[s] : 0.f;
   const bool check = A.clear_min > 0.f;
   const int o0 = check ? A.obs_off[s] : 0, m = check ? A.obs_off[s + 1] - o0 : 0;
+  if (check && !obstacles_ok(o0, m, sd.m)) {  // the post-check cannot read this scene's obstacles
+    if (r == 0) A.cost[g] = __builtin_nanf("");
+    return;
+  }
   const float dt = sd.t_f / (float)(n - 1);
   const float ia = 1.f / A.a, ib = 1.f / A.b;
   const float* P0 = T + tab_basis(n, 0);
@@ -176,7 +180,8 @@ __global__ void k_controls(ControlArgs A) {
   const int b = A.best[s];
   const int sid = A.shape_id[s];
   const int g0 = A.goal_off[s], g1 = A.goal_off[s + 1];
-  const bool bad = sid < 0 || sid >= A.n_shapes || b < 0 || g0 + b >= g1 || g0 + b >= A.n_goals;
+  const bool bad = sid < 0 || sid >= A.n_shapes || b < 0 || g0 < 0 || g0 + b >= g1 || g0 + b >= A.n_goals ||
+                   !obstacles_ok(A.obs_off[s], A.obs_off[s + 1] - A.obs_off[s], A.shapes[sid].m);
   float* acc = A.accel + (size_t)s * A.stride;
   float* st = A.steer + (size_t)s * A.stride;
   if (bad) {

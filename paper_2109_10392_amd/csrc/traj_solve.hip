@@ -454,6 +454,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   if (scene < 0) return;
   if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
   const int g0 = sh[1];
+  if (g0 < 0) return;  // goal offsets out of contract: nothing to touch
   const int g1 = min(min(g0 + GPW, (int)A.goal_off[scene + 1]), A.n_goals);
   const int sid = A.shape_id[scene];
   const int o0 = A.obs_off[scene];
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   bool bad = sid < 0 || sid >= A.n_shapes;
   ShapeDesc sd = {};
   if (!bad) sd = A.shapes[sid];
-  bad = bad || m_scene != sd.m || sd.n > WAVE * S * WPG || sd.n < NC;
+  bad = bad || !obstacles_ok(o0, m_scene, sd.m) || sd.n > WAVE * S * WPG || sd.n < NC;
   const int tid = threadIdx.x;
   const int g = g0 + (tid >> 6) / WPG;
   const bool writer = ((tid >> 6) % WPG) == 0;

@@ -99,3 +99,47 @@ def test_non_finite_inputs_mark_only_their_goals(T, kernel, waves, precision):
     b_ref = ref["best"][1]
     assert out["best"][2] == (keep[b_ref] if b_ref >= 0 else -1)
     assert out["best"][0] == ref["best"][0]
+
+
+@pytest.mark.parametrize("kernel,waves,precision", CASES)
+def test_obstacle_range_before_the_array_marks_its_scene(T, kernel, waves, precision):
+    """A scene whose obstacle range starts before the obstacle array (its count
+    still that of its shape) is marked like one of unknown shape: NaN residuals,
+    a NaN cost with the collision post-check, no best goal; its obstacles are never
+    read. The next scene is solved exactly as on its own."""
+    import torch
+    s0, s1 = S.make_scene(41, 12, 12), S.make_scene(42, 12, 12)
+    batch = S.Batch([s0, s1])
+    all_obs = batch.obs()
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile(kernel, 16, True, waves)
+    db = T.DeviceBatch.from_batch(batch)
+    # ranges [-6, 6) and [6, 18): both of the shape's 12 obstacles, the first out of the array
+    db.obs_off.copy_(torch.tensor([-6, 6, 18], dtype=torch.int32, device="cuda"))
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, ITERS, kernel=kernel, precision=precision)
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    solver.score(db, st, v_ref, cost, best, clear_min=1.0)
+    torch.cuda.synchronize()
+    resid, c, cost, best = st.resid.cpu().numpy(), st.c.cpu().numpy(), cost.cpu().numpy(), best.cpu().numpy()
+    solver.close()
+    n0 = s0.goals.shape[0]
+    assert np.all(np.isnan(resid[:, :n0])) and np.all(np.isnan(cost[:n0])) and best[0] == -1
+
+    ref_scene = dataclasses.replace(s1, obs=all_obs[6:18].copy())
+    solver = T.Solver(PARAMS, S.Batch([ref_scene]).shapes())
+    solver.set_tile(kernel, 16, True, waves)
+    rdb = T.DeviceBatch.from_batch(S.Batch([ref_scene]))
+    rst = T.DeviceState.empty(ref_scene.goals.shape[0])
+    solver.solve(rdb, rst, ITERS, kernel=kernel, precision=precision)
+    rcost = torch.zeros(ref_scene.goals.shape[0], device="cuda")
+    rbest = torch.zeros(1, device="cuda", dtype=torch.int32)
+    solver.score(rdb, rst, v_ref[1:], rcost, rbest, clear_min=1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(c[..., n0:], rst.c.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(resid[:, n0:], rst.resid.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(cost[n0:], rcost.cpu().numpy(), equal_nan=True)
+    assert best[1] == int(rbest.item())
+    solver.close()
