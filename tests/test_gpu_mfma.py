@@ -120,16 +120,22 @@ def test_bf16x3_precision_report(T):
         res_err = np.abs(out["resid"][:3] - st.resid[:3]).max(0)
         assert np.all(np.isfinite(out["c"])) and np.all(np.isfinite(out["resid"]))
         cg = out["c"].astype(np.float64)
+        # boundary constraints of eq. 8b at the computed coefficients (relative to max(|b|, 1))
+        b_x, b_y, b_psi = O.boundary_values(sc.ego, sc.goals)
+        cons = max(float(np.max(np.abs(A @ cg[ax] - b)) / max(1.0, float(np.max(np.abs(b)))))
+                   for A, ax, b in ((prob.A_x, 0, b_x), (prob.A_y, 1, b_y), (prob.A_psi, 2, b_psi)))
         v0 = float(sc.ego[2])
         cost_g = O.meta_cost(prob, cg[0], cg[1], cg[2], 0, v_ref=v0)
         cost_o = O.meta_cost(prob, st.c_x, st.c_y, st.c_psi, 0, v_ref=v0)
         bg, bo = O.best_goal(cost_g), O.best_goal(cost_o)
         near = bg == bo or (bg >= 0 and bo >= 0 and abs(cost_o[bg] - cost_o[bo]) <= 1e-3 * max(1.0, abs(cost_o[bo])))
         rows.append(dict(seed=seed, coef_err_max=float(err[~und].max()), coef_err_median=float(np.median(err[~und])),
-                         resid_abs_err_max=float(res_err[~und].max()), best_gpu=bg, best_oracle=bo,
+                         resid_abs_err_max=float(res_err[~und].max()), constraint_resid_max=cons,
+                         best_gpu=bg, best_oracle=bo,
                          best_match=bool(near), undetermined=np.flatnonzero(und).tolist()))
         print(json.dumps(rows[-1]))
     with open(report_path("bf16x3_precision_report.json"), "w") as f:
         json.dump(rows, f, indent=1)
     assert sum(r["best_match"] for r in rows) >= 9
     assert max(r["coef_err_max"] for r in rows) <= TOL_BF16X3
+    assert max(r["constraint_resid_max"] for r in rows) <= 1e-3
