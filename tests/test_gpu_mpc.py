@@ -119,6 +119,26 @@ def test_closed_loop_warm_starts_run(M, warm):
     assert 0 < m["mean_iterations_per_cycle"] <= 100
 
 
+def test_closed_loop_with_the_split_bf16_solver(M):
+    """The same 64 cold-started episodes in FP32 and with the split-BF16 solver
+    over 10 cycles: the plans take the same iterations to the stopping rule and
+    the loop's statistics agree (the solver forms differ by rounding only)."""
+    import torch
+    ms = {}
+    for precision in ("fp32", "bf16x3"):
+        cl = M.ClosedLoop(range(64), iters=100, warm="cold", clear_min=1.0, precision=precision)
+        for _ in range(10):
+            cl.cycle()
+        torch.cuda.synchronize()
+        assert np.all(np.isfinite(cl.db.ego.cpu().numpy()))
+        ms[precision] = cl.metrics(10)
+        print(precision, ms[precision])
+    a, b = ms["fp32"], ms["bf16x3"]
+    assert abs(a["mean_iterations_per_cycle"] - b["mean_iterations_per_cycle"]) <= 0.02 * a["mean_iterations_per_cycle"]
+    assert abs(a["mean_speed"] - b["mean_speed"]) <= 0.01 * a["mean_speed"]
+    assert a["episodes_with_collision"] == b["episodes_with_collision"]
+
+
 def test_right_lane_goals_match_the_oracle(M):
     import torch
     cl = M.ClosedLoop(range(5), iters=5, scenario="right_lane", v_max=25.0)
