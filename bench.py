@@ -53,11 +53,11 @@ def sources_hash(files):
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel, waves):
-    """Bytes per launch if the profiled kernel and sources are what runs, else None."""
+def measured_traffic(workload, kernel, waves, precision):
+    """Bytes per launch if the profiled kernel (FP32 form) and sources are what runs, else None."""
     m = MEASURED_TRAFFIC.get(workload)
     expected = {"dense": ("wave", 2), "uneven": ("group", None)}[workload]
-    if m is None or kernel != expected[0] or (expected[1] is not None and waves != expected[1]):
+    if m is None or precision != "fp32" or kernel != expected[0] or (expected[1] is not None and waves != expected[1]):
         return None
     return m["bytes_per_launch"] if sources_hash(m["sources"]) == m["sha256"] else None
 
@@ -353,7 +353,7 @@ def main():
            "waves": waves},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(args.workload, kernel, waves),
+                     "traffic": measured_traffic(args.workload, kernel, waves, args.precision),
                      "kernel": {"wave": "k_am (wave kernel)", "mfma": "k_am_mfma", "group": "k_am_group"}[kernel],
                      "kernel_ms": solve_avg_s * 1e3,
                      "algorithmic_flop_per_launch": flops},
