@@ -231,23 +231,26 @@ def test_bf16x3_group_precision_report(T):
 _UNEVEN_ORACLE = {}  # scene index -> (prob, oracle state) of its sampled goals
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_uneven_full_batch_sampled(T, precision):
+@pytest.mark.parametrize("kernel,precision", [("group", "fp32"), ("group", "bf16x3"), ("wave", "fp32"),
+                                              ("mfma", "fp32"), ("mfma", "bf16x3")])
+def test_uneven_full_batch_sampled(T, kernel, precision):
     """The uneven workload at its full size (512 scenes, 118,830 goals, T in {50,
-    100, 150}, 4-64 obstacles) in the launch configuration its benchmark times
-    (group kernel, 16 goals, persistent, 100 iterations), in FP32 and in the
-    split-BF16 form: the first, middle and last goal of twelve scenes spanning the
-    shapes against the oracle (gates 1e-4 and 1e-3), and the ranking of those
-    scenes against the oracle's meta-cost of the same coefficients."""
+    100, 150}, 4-64 obstacles), 100 iterations: in the launch configuration its
+    benchmark times (group kernel, 16 goals, persistent) and on the other two
+    kernels (wave kernel with two waves per goal, MFMA kernel), in FP32 and in
+    the split-BF16 form. The first, middle and last goal of twelve scenes spanning
+    the shapes are checked against the oracle (gates 1e-4 and 1e-3), and the
+    ranking of those scenes against the oracle's meta-cost of the same
+    coefficients."""
     import torch
     tol = TOL if precision == "fp32" else TOL_BF16X3
     batch = S.workload_uneven(0)
     assert batch.n_scenes == 512 and batch.n_goals == 118830
     solver = T.Solver(PARAMS, batch.shapes())
-    solver.set_tile("group", 16, True)
+    solver.set_tile(kernel, 16, True, 2 if kernel == "wave" else 1)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
-    solver.solve(db, st, 100, precision=precision)
+    solver.solve(db, st, 100, kernel=kernel, precision=precision)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
     cost = torch.zeros(batch.n_goals, device="cuda")
     best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
