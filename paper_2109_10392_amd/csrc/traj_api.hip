@@ -13,6 +13,8 @@
 namespace traj {
 hipError_t launch_debug_reduce(const float* in, float* out, int r, hipStream_t stream);
 hipError_t launch_debug_atan2(const float* y, const float* x, float* out, int n, hipStream_t stream);
+// raises the MFMA kernel's dynamic LDS on the current device (once per need; takes a lock)
+hipError_t mfma_reserve_smem(size_t smem);
 }
 
 namespace {
@@ -166,6 +168,12 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
       return hip_fail(e, "traj_setup: occupancy query");
     }
     h->resident_blocks[mode] = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  // the MFMA kernel's dynamic LDS for this handle's shapes (larger handles are
+  // refused at dispatch)
+  if ((e = traj::mfma_reserve_smem(traj::mfma_smem_bytes(h->max_n, h->max_m))) != hipSuccess) {
+    traj_destroy(h);
+    return hip_fail(e, "traj_setup: LDS reservation");
   }
   *handle_out = h;
   return TRAJ_OK;

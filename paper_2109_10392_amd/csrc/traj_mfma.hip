@@ -25,6 +25,8 @@
 //   BF16x3: v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo (bf16 each):
 //           hi*hi + lo*hi + hi*lo in two instructions (K = 32 holds hi and lo of
 //           16 K values), FP32 accumulation, for every contraction and apply.
+#include <mutex>
+
 #include "traj_mma.h"
 
 namespace traj {
@@ -511,6 +513,26 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
 
 }  // namespace
 
+// The dynamic LDS the MFMA kernel may take is raised once per device, to the
+// largest need seen, under a lock: setup reserves each handle's need, so the
+// launches (which a caller may capture into a graph) make no attribute calls.
+hipError_t mfma_reserve_smem(size_t smem) {
+  static std::mutex lock;
+  static int reserved[64] = {};  // bytes per device
+  if (smem <= 65536 || smem > MFMA_SMEM_LIMIT) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> guard(lock);
+  if (dev >= 0 && dev < 64 && (int)smem <= reserved[dev]) return hipSuccess;
+  for (const void* fn : {(const void*)k_am_mfma<TRAJ_MODE_FP32>, (const void*)k_am_mfma<TRAJ_MODE_BF16X3>}) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+  }
+  if (dev >= 0 && dev < 64) reserved[dev] = (int)smem;
+  return hipSuccess;
+}
+
 size_t mfma_smem_bytes(int max_n, int max_m) {
   const int W = (max_n + TILE - 1) / TILE;
   const int mm = max_m > 0 ? max_m : 1;
@@ -528,7 +550,7 @@ hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int
   const void* fn = mode == TRAJ_MODE_BF16X3 ? (const void*)k_am_mfma<TRAJ_MODE_BF16X3>
                                             : (const void*)k_am_mfma<TRAJ_MODE_FP32>;
   if (smem > 65536) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    hipError_t e = mfma_reserve_smem(smem);  // a no-op once setup has reserved it
     if (e != hipSuccess) return e;
   }
   if (mode == TRAJ_MODE_BF16X3)

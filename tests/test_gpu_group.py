@@ -167,13 +167,17 @@ def test_group_repeated_solves_reuse_the_work_list(T):
     solver.close()
 
 
-def test_group_hipgraph_replay_matches_eager(T):
-    """Work list + persistent solve + scoring captured once and replayed; every
-    replay (with eager work of the program in between) equals the eager result."""
+@pytest.mark.parametrize("kernel,waves,precision", [("group", 1, "fp32"), ("group", 1, "bf16x3"),
+                                                    ("wave", 2, "fp32"), ("mfma", 1, "fp32")])
+def test_hipgraph_replay_matches_eager(T, kernel, waves, precision):
+    """Solve + scoring (for the group kernel with its goal order and work list)
+    captured once and replayed; every replay (with eager work of the program in
+    between) equals the eager result. The MFMA launch here needs more than 64 KB
+    of LDS, reserved at setup."""
     import torch
     batch = ragged_batch()
     solver = T.Solver(PARAMS, batch.shapes())
-    solver.set_tile("group", 16, True)
+    solver.set_tile(kernel, 16, True, waves)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
@@ -181,7 +185,7 @@ def test_group_hipgraph_replay_matches_eager(T):
     best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
 
     def step():
-        solver.solve(db, st, 30)
+        solver.solve(db, st, 30, kernel=kernel, precision=precision)
         solver.score(db, st, v_ref, cost, best)
 
     step()  # eager reference (also sizes the work buffer outside the capture)
