@@ -356,6 +356,32 @@ def test_meta_cost_and_argmin_by_explicit_loops():
     assert O.best_goal([np.inf, np.inf]) == -1
 
 
+def test_meta_cost_closed_forms_on_uniform_motion():
+    """Eqs. 25 and 26 on trajectories with closed-form samples: c_x on the line
+    v t_f k/10 (a Bernstein basis reproduces it, so the speed is v at every
+    sample), c_y and c_psi constant (y and the heading constant, their rates 0).
+    Then eq. 25 is n (v - v_ref)^2, eq. 26 is n (w1 (v - v_ref)^2 + w2 (y - y_rl)^2),
+    and the heading filter drops exactly the goals with |psi| > 13 degrees."""
+    n, t_f = 100, 10.0
+    prob = O.Problem(n, t_f, 0, PARAMS)
+    k = np.arange(11)
+    v = np.array([12.0, 20.0, 25.0, 18.0])
+    y = np.array([0.0, -3.5, 3.5, 7.0])
+    psi = np.array([0.0, 0.2, -0.2, 0.25])  # the last beyond 13 degrees (0.2269 rad)
+    c_x = (v[None, :] * t_f) * (k[:, None] / 10.0)
+    c_y = np.repeat(y[None, :], 11, axis=0)
+    c_p = np.repeat(psi[None, :], 11, axis=0)
+    v_ref, w1, w2, y_rl = 22.0, 0.7, 0.3, -3.5
+    c25 = O.meta_cost(prob, c_x, c_y, c_p, 0, v_ref=v_ref)
+    c26 = O.meta_cost(prob, c_x, c_y, c_p, 1, v_ref=v_ref, w1=w1, w2=w2, y_rl=y_rl)
+    e25 = n * (v - v_ref) ** 2
+    e26 = n * (w1 * (v - v_ref) ** 2 + w2 * (y - y_rl) ** 2)
+    assert np.allclose(c25[:3], e25[:3], rtol=1e-10, atol=1e-9)
+    assert np.allclose(c26[:3], e26[:3], rtol=1e-10, atol=1e-9)
+    assert c25[3] == np.inf and c26[3] == np.inf
+    assert O.best_goal(c25) == 1 and O.best_goal(c26) == 1
+
+
 def test_default_constants_are_the_papers():
     with open(os.path.join(HERE, "golden", "paper_constants.json")) as f:
         gold = json.load(f)
