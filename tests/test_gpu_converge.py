@@ -78,11 +78,16 @@ def test_skipped_scenes_are_left_untouched(T, kernel):
             assert np.array_equal(c[:, :, sl], ref[0][:, :, sl]), s
 
 
-def test_converge_stops_at_the_first_chunk_meeting_the_rule(T):
+@pytest.mark.parametrize("kernel,waves,precision", [("group", 1, "fp32"), ("group", 1, "bf16x3"),
+                                                    ("wave", 2, "fp32"), ("mfma", 1, "bf16x3")])
+def test_converge_stops_at_the_first_chunk_meeting_the_rule(T, kernel, waves, precision):
+    """Every scene stops at the first chunk of 5 iterations where its best goal
+    meets the rule (R10), and its state equals a plain solve of that many
+    iterations bitwise; on each kernel and precision form."""
     import torch
     batch = S.Batch([S.workload_small(s).scenes[0] for s in range(6)])
     solver = T.Solver(PARAMS, batch.shapes())
-    solver.set_tile("group", 16, True)
+    solver.set_tile(kernel, 16, True, waves)
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(batch.n_goals)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
@@ -90,7 +95,7 @@ def test_converge_stops_at_the_first_chunk_meeting_the_rule(T):
     best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
     its = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
     tol, cap = 1e-3, 300
-    solver.converge(db, st, v_ref, cost, best, its, max_iters=cap, chunk=5, tol=tol)
+    solver.converge(db, st, v_ref, cost, best, its, max_iters=cap, chunk=5, tol=tol, precision=precision)
     torch.cuda.synchronize()
     c = st.c.cpu().numpy()
     done = st.scene_done.cpu().numpy()
@@ -104,7 +109,7 @@ def test_converge_stops_at_the_first_chunk_meeting_the_rule(T):
         one = S.Batch([batch.scenes[s]])
         dbs = T.DeviceBatch.from_batch(one, shapes=batch.shapes())
         sts = T.DeviceState.empty(one.n_goals)
-        solver.solve(dbs, sts, k)
+        solver.solve(dbs, sts, k, precision=precision)
         vr = v_ref[s:s + 1]
         cs = torch.zeros(one.n_goals, device="cuda")
         bs = torch.zeros(1, device="cuda", dtype=torch.int32)
