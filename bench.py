@@ -33,13 +33,13 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "6217d8b27f38d60cfafb321b9383f126cbcb149aa5900385add25558415ea4c6",
+              "sha256": "2bd5d67b0ee785d4c0d96fb0ec0d2f3d03575cc6d4ed18850e6f4129c436b09e",
               "bytes_per_launch": int((279.5 * 2.0 + 2272.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "c383e081dd089b39b24dc941542c29e2f5c71b68dd0b5519c4cf46f297acca3b",
-               "bytes_per_launch": int((77001.5 * 2.0 + 278252.4) * 1024),
+               "sha256": "560aac43abd4c468e57ba1d6f7b0a395a6832982fe42592093a29d718ee5b375",
+               "bytes_per_launch": int((84134.3 * 2.0 + 277690.0) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 

@@ -95,7 +95,8 @@ int check_batch(const Handle* h, const traj_batch* b) {
 int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
                void* stream, bool reuse_order);
 int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
-               int32_t* best, void* stream, const int32_t* skip = nullptr);
+               int32_t* best, void* stream, const int32_t* skip = nullptr,
+               const traj::ConvergeCheck* check = nullptr);
 
 }  // namespace
 
@@ -225,13 +226,13 @@ int traj_converge(void* handle, const traj_batch* batch, traj_state* state, cons
     // the first chunk starts as the caller asked; later chunks resume the state
     const uint32_t f = c == 0 ? flags : ((flags & keep) | TRAJ_INIT_FROM_STATE);
     if ((rc = solve_impl(h, batch, state, it, 0.f, f, stream, c > 0)) != TRAJ_OK) return rc;
-    // scenes converged in an earlier chunk are neither iterated nor re-scored
-    if ((rc = score_impl(h, batch, state, mc, cost, best, stream, c > 0 ? state->scene_done : nullptr)) != TRAJ_OK)
-      return rc;
+    // scenes converged in an earlier chunk are neither iterated nor re-scored; the
+    // scoring also applies the stopping rule to the others
     if (state->resid == nullptr) return fail(TRAJ_E_INVAL, "state.resid is required");
-    e = traj::launch_converge_check(batch->goal_off, state->resid, best, batch->n_scenes, batch->n_goals, it, tol,
-                                    state->scene_done, scene_iters, st);
-    if (e != hipSuccess) return hip_fail(e, "traj_converge");
+    const traj::ConvergeCheck check = {state->resid, state->scene_done, scene_iters, it, tol};
+    if ((rc = score_impl(h, batch, state, mc, cost, best, stream, c > 0 ? state->scene_done : nullptr, &check)) !=
+        TRAJ_OK)
+      return rc;
     done += it;
   }
   return TRAJ_OK;
@@ -315,7 +316,7 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
 }
 
 int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
-               int32_t* best, void* stream, const int32_t* skip) {
+               int32_t* best, void* stream, const int32_t* skip, const traj::ConvergeCheck* check) {
   if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
   int rc = check_batch(h, batch);
   if (rc != TRAJ_OK) return rc;
@@ -352,7 +353,7 @@ int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, cons
   a.skip = skip;
   a.cost = cost;
   a.best = best;
-  hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream);
+  hipError_t e = traj::launch_score(a, h->max_n, (hipStream_t)stream, check);
   if (e != hipSuccess) return hip_fail(e, "traj_score launch");
   return TRAJ_OK;
 }

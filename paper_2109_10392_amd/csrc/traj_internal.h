@@ -190,7 +190,17 @@ hipError_t launch_solve(const SolveArgs& a, int max_n, int max_m, int waves, hip
 hipError_t launch_solve_mfma(const SolveArgs& a, int mode, int G, int max_n, int max_m, hipStream_t stream);
 size_t mfma_smem_bytes(int max_n, int max_m);
 constexpr size_t MFMA_SMEM_LIMIT = 150 * 1024;  // LDS the MFMA kernel may take per workgroup
-hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream);
+// Stopping rule of the chunked solve, applied by the argmin kernel when done is set:
+// per scene not yet converged, scene_iters += iters and done = 1 once the residual
+// max(r_obs, r_acc, r_nh) of its best goal is at or below tol.
+struct ConvergeCheck {
+  const float* resid;
+  int32_t* done;
+  int32_t* scene_iters;
+  int iters;
+  float tol;
+};
+hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream, const ConvergeCheck* check = nullptr);
 hipError_t launch_controls(const ControlArgs& a, hipStream_t stream);
 
 // Group kernel (one wavefront per goal group, cost-sorted work list).
@@ -199,12 +209,8 @@ int64_t group_work_ints(int n_scenes, int n_goals, int G);
 hipError_t group_blocks_per_cu(int mode, int* blocks);
 hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
                               int32_t* work, bool reuse_order, hipStream_t stream);
-// Convergence bookkeeping (traj_converge): zero the per-scene flags and counters;
-// after a chunk of `iters` iterations and scoring, add the chunk to every active
-// scene and mark it done when its best goal meets max(r_obs, r_acc, r_nh) <= tol.
+// Convergence bookkeeping (traj_converge): zero the per-scene flags and counters
+// (the check after each chunk runs in the argmin kernel, see ConvergeCheck).
 hipError_t launch_converge_reset(int32_t* done, int32_t* scene_iters, int n_scenes, hipStream_t stream);
-hipError_t launch_converge_check(const int32_t* goal_off, const float* resid, const int32_t* best, int n_scenes,
-                                 int n_goals, int iters, float tol, int32_t* done, int32_t* scene_iters,
-                                 hipStream_t stream);
 
 }  // namespace traj

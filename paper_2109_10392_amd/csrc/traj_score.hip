@@ -125,13 +125,22 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
   if (r == 0) A.cost[g] = (pmax > A.psi_max || hit) ? __builtin_inff() : acc;
 }
 
-// One workgroup per scene: lowest index attaining the minimum finite cost.
-__global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
+// One workgroup per scene: lowest index attaining the minimum finite cost. In a
+// chunked solve (C.done set) the same thread then applies the stopping rule to
+// the scene: it adds the chunk's iterations and marks the scene converged when
+// the residual max(r_obs, r_acc, r_nh) of its best goal is at or below tol (a
+// scene whose goals are all filtered keeps iterating). Converged scenes are
+// skipped from the start (A.skip is the same array).
+__global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A, ConvergeCheck C) {
   __shared__ float sv[SCORE_THREADS / WAVE];
   __shared__ int si[SCORE_THREADS / WAVE];
   const int s = blockIdx.x;
   if (A.skip != nullptr && A.skip[s] != 0) return;
   const int g0 = A.goal_off[s], g1 = min((int)A.goal_off[s + 1], A.n_goals);
+  if (g0 < 0) {  // goal offsets out of contract: no goal is read
+    if (threadIdx.x == 0) A.best[s] = -1;
+    return;
+  }
   float best = __builtin_inff();
   int bi = 0x7fffffff;
   for (int g = g0 + (int)threadIdx.x; g < g1; g += SCORE_THREADS) {
@@ -163,7 +172,17 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A) {
         bi = si[w];
       }
     }
-    A.best[s] = (bi == 0x7fffffff) ? -1 : bi;
+    const int b = (bi == 0x7fffffff) ? -1 : bi;
+    A.best[s] = b;
+    if (C.done != nullptr && C.done[s] == 0) {
+      C.scene_iters[s] += C.iters;
+      const int g = g0 + b;
+      if (b >= 0 && g < A.n_goals) {
+        const float worst = fmaxf(fmaxf(C.resid[0 * A.n_goals + g], C.resid[1 * A.n_goals + g]),
+                                  C.resid[2 * A.n_goals + g]);
+        if (worst <= C.tol) C.done[s] = 1;
+      }
+    }
   }
 }
 
@@ -238,23 +257,6 @@ __global__ void k_converge_reset(int32_t* done, int32_t* scene_iters, int n_scen
   }
 }
 
-// Stopping rule of the chunked solve: a scene is converged when the residual
-// max(r_obs, r_acc, r_nh) of its current best goal is at or below tol (checked
-// after every chunk; a scene whose goals are all filtered keeps iterating).
-__global__ void k_converge_check(const int32_t* __restrict__ goal_off, const float* __restrict__ resid,
-                                 const int32_t* __restrict__ best, int n_scenes, int n_goals, int iters, float tol,
-                                 int32_t* __restrict__ done, int32_t* __restrict__ scene_iters) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_scenes || done[s] != 0) return;
-  scene_iters[s] += iters;
-  const int b = best[s];
-  if (b < 0) return;
-  const int g = goal_off[s] + b;
-  if (g < 0 || g >= n_goals) return;
-  const float worst = fmaxf(fmaxf(resid[0 * n_goals + g], resid[1 * n_goals + g]), resid[2 * n_goals + g]);
-  if (worst <= tol) done[s] = 1;
-}
-
 }  // namespace
 
 hipError_t launch_controls(const ControlArgs& a, hipStream_t stream) {
@@ -270,16 +272,7 @@ hipError_t launch_converge_reset(int32_t* done, int32_t* scene_iters, int n_scen
   return hipGetLastError();
 }
 
-hipError_t launch_converge_check(const int32_t* goal_off, const float* resid, const int32_t* best, int n_scenes,
-                                 int n_goals, int iters, float tol, int32_t* done, int32_t* scene_iters,
-                                 hipStream_t stream) {
-  if (n_scenes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_converge_check, dim3((n_scenes + 255) / 256), dim3(256), 0, stream, goal_off, resid, best,
-                     n_scenes, n_goals, iters, tol, done, scene_iters);
-  return hipGetLastError();
-}
-
-hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream) {
+hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream, const ConvergeCheck* check) {
   (void)max_n;
   if (a.n_goals > 0) {
     const int blocks = (a.n_goals + COST_GOALS - 1) / COST_GOALS;
@@ -287,7 +280,9 @@ hipError_t launch_score(const ScoreArgs& a, int max_n, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (a.n_scenes > 0) hipLaunchKernelGGL(k_argmin, dim3(a.n_scenes), dim3(SCORE_THREADS), 0, stream, a);
+  const ConvergeCheck none = {};
+  if (a.n_scenes > 0)
+    hipLaunchKernelGGL(k_argmin, dim3(a.n_scenes), dim3(SCORE_THREADS), 0, stream, a, check ? *check : none);
   return hipGetLastError();
 }
 
