@@ -258,7 +258,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "goals are independent, so a multi-GPU run would shard scenes with no exchange inside the loop.",
               file=sys.stderr)
         sys.exit(2)

@@ -13,3 +13,10 @@ def test_traffic_only_for_the_profiled_configuration():
         got = bench.measured_traffic(workload, kernel, waves, "fp32")
         # the profiled configuration: the figure while its sources are unchanged, else nothing
         assert got == (m["bytes_per_launch"] if bench.sources_hash(m["sources"]) == m["sha256"] else None)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert out.returncode != 0 and "one GPU" in out.stdout + out.stderr
