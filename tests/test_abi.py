@@ -132,3 +132,54 @@ def test_closed_loop_calls_validate_on_the_host():
                            None) == -1
     assert L.traj_mpc_shift(None, ctypes.byref(b), ctypes.byref(st), ctypes.byref(eps), None) == -1
     assert L.traj_last_error()
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "traj.h"
+#include "traj_mlp.h"
+#include "traj_mpc.h"
+#include "traj_frenet.h"
+
+int main(void) {
+  /* host-side validation only: no device work is reached */
+  void *h = (void *)0;
+  traj_params p;
+  memset(&p, 0, sizeof p);
+  p.n_coef = 11; /* the rest zero: a <= 0 is rejected */
+  traj_shape s = {100, 10.0f, 10};
+  int rc = traj_setup(&p, &s, 1, (void *)0, &h);
+  const char *msg = traj_last_error();
+  printf("setup %d %s\n", rc, msg);
+  if (rc != TRAJ_E_INVAL || msg == (const char *)0 || msg[0] == 0 || h != (void *)0) return 1;
+  rc = traj_solve_batch((void *)0, (const traj_batch *)0, (traj_state *)0, 10, 0.0f, 0u, (void *)0);
+  printf("solve %d %s\n", rc, traj_last_error());
+  if (rc != TRAJ_E_INVAL) return 2;
+  return traj_destroy((void *)0) == TRAJ_OK ? 0 : 3;
+}
+"""
+
+
+def test_headers_are_c_and_the_library_links_from_c(tmp_path):
+    """The boundary is a C ABI: every header compiles as C99 with warnings as
+    errors, and a C program linked against libtraj.so gets the host-side
+    validation errors with their messages (no GPU work)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    lib_dir = os.path.dirname(T.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+           str(src), "-o", str(exe), "-L", lib_dir, "-l:libtraj.so", "-Wl,-rpath," + lib_dir]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ)
+    env["LD_LIBRARY_PATH"] = "/opt/rocm/lib:" + env.get("LD_LIBRARY_PATH", "")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("setup -1 ")
