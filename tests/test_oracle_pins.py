@@ -388,3 +388,210 @@ def test_default_constants_are_the_papers():
     assert PARAMS["a"] == gold["ellipse_a"]["value"] and PARAMS["b"] == gold["ellipse_b"]["value"]
     assert abs(PARAMS["psi_max"] - math.radians(gold["heading_filter_deg"]["value"])) < 1e-15
     assert S.workload_small(0).scenes[0].goals.shape[0] == gold["batch_size_l"]["value"]
+
+
+# ------------------------------------------- residual blocks and predictions (eqs. 8c, 9)
+
+def test_obstacle_predictions_by_hand():
+    """Constant-velocity predictions (Sec. III, assumption 3), stacked obstacle-major
+    as F_o stacks P once per obstacle (eq. 7): values worked out by hand."""
+    obs = np.array([[1.0, 2.0, 3.0, -0.5], [-4.0, 1.75, 0.25, 2.0]])
+    t = np.array([0.0, 0.5, 2.0])
+    xi_x, xi_y = O.obstacle_predictions(obs, t)
+    assert np.array_equal(xi_x, [1.0, 2.5, 7.0, -4.0, -3.875, -3.5])
+    assert np.array_equal(xi_y, [2.0, 1.75, 1.0, 1.75, 2.75, 5.75])
+
+
+def _moving_obstacle_scene():
+    """An 11-goal scene whose obstacles also move sideways (vy != 0), so that
+    every term of the prediction x_j + v_j t enters the residuals."""
+    sc = S.workload_small(7).scenes[0]
+    rng = np.random.default_rng(70)
+    obs = np.array(sc.obs, np.float64)
+    obs[:, 3] = rng.uniform(-0.6, 0.6, obs.shape[0])
+    return sc, obs
+
+
+def _blocks_by_loops(prob, obs, st):
+    """r_obs, r_acc, r_nh, r_psi per goal, summed sample by sample.
+
+    Rows of F c - g (eq. 8c) with g written out per eq. 9: obstacle rows
+    x(t_i) - (xi_x,j(t_i) + a d cos alpha), y(t_i) - (xi_y,j(t_i) + b d sin alpha);
+    acceleration rows x''(t_i) - d_a cos alpha_a, y''(t_i) - d_a sin alpha_a;
+    velocity rows x'(t_i) - v cos psi(t_i), y'(t_i) - v sin psi(t_i); heading
+    atan2(y', x') - psi. The split variables are re-derived from their closed forms
+    (eq. 22 and the clipped 1-D minimisers of eqs. 15, 16, eq. 21) with the
+    predictions xi_j(t_i) = p_j + v_j t_i computed here, and checked against the
+    oracle's on the way. Uses neither build_g, F nor residuals."""
+    n, m, a, b = prob.n, prob.m, prob.a, prob.b
+    B = st.c_x.shape[1]
+    out = np.zeros((4, B))
+    for l in range(B):
+        acc = [0.0, 0.0, 0.0, 0.0]
+        for i in range(n):
+            ti = i * prob.t_f / (n - 1)
+            x, y = float(prob.P[i] @ st.c_x[:, l]), float(prob.P[i] @ st.c_y[:, l])
+            xd, yd = float(prob.Pd[i] @ st.c_x[:, l]), float(prob.Pd[i] @ st.c_y[:, l])
+            xdd, ydd = float(prob.Pdd[i] @ st.c_x[:, l]), float(prob.Pdd[i] @ st.c_y[:, l])
+            psi = float(prob.P[i] @ st.c_psi[:, l])
+            for j in range(m):
+                dx = x - (obs[j, 0] + obs[j, 2] * ti)
+                dy = y - (obs[j, 1] + obs[j, 3] * ti)
+                al = math.atan2(a * dy, b * dx)
+                d = max(1.0, math.sqrt((dx / a) ** 2 + (dy / b) ** 2))
+                assert abs(al - st.alpha[j * n + i, l]) <= 1e-12 and abs(d - st.d[j * n + i, l]) <= 1e-12 * d
+                acc[0] += (dx - a * d * math.cos(al)) ** 2 + (dy - b * d * math.sin(al)) ** 2
+            al_a = math.atan2(ydd, xdd)
+            d_a = min(prob.a_max, math.hypot(xdd, ydd))
+            v = min(max(math.hypot(xd, yd), prob.v_min), prob.v_max)
+            assert abs(v - st.v[i, l]) <= 1e-12 * v and abs(d_a - st.d_a[i, l]) <= 1e-12 * max(1.0, d_a)
+            acc[1] += (xdd - d_a * math.cos(al_a)) ** 2 + (ydd - d_a * math.sin(al_a)) ** 2
+            acc[2] += (xd - v * math.cos(psi)) ** 2 + (yd - v * math.sin(psi)) ** 2
+            acc[3] += (math.atan2(yd, xd) - psi) ** 2
+        out[:, l] = np.sqrt(acc)
+    return out
+
+
+@pytest.mark.parametrize("iters", [0, 3])
+def test_residual_blocks_by_explicit_loops(iters):
+    """The four residual components (rows of eq. 8c per the Fig. 3a caption and the
+    convergence paragraph of Sec. IV; heading per eq. 13) recomputed sample by sample.
+    After zero iterations they are those of the starting point."""
+    sc, obs = _moving_obstacle_scene()
+    prob = O.Problem(sc.n_time, sc.t_f, obs.shape[0], PARAMS)
+    st = O.solve(prob, sc.ego, obs, sc.goals, iters)
+    ref = _blocks_by_loops(prob, obs, st)
+    assert np.all(ref[0] > 0) or iters == 0  # obstacle rows are exercised
+    assert np.allclose(st.resid, ref, rtol=1e-10, atol=1e-12)
+    # the blocks differ on this scene's lane changes, so a swap of two of them shows
+    assert np.max(np.abs(ref[1] - ref[2])) > 1e-2
+
+
+def test_residual_pin_catches_planted_mistakes(monkeypatch):
+    """Planted in the oracle, on the CPU: (a) the velocity and acceleration row
+    blocks of F_ax stacked in the wrong order; (b) r_acc and r_nh swapped in the
+    output. The loop pin above must reject both."""
+    sc, obs = _moving_obstacle_scene()
+    real_build_F = O.build_F
+
+    def swapped_F(P, Pd, Pdd, m):
+        return real_build_F(P, Pdd, Pd, m)  # F_ax = [F_o; P'; P''] instead of [F_o; P''; P']
+
+    monkeypatch.setattr(O, "build_F", swapped_F)
+    prob = O.Problem(sc.n_time, sc.t_f, obs.shape[0], PARAMS)
+    st = O.solve(prob, sc.ego, obs, sc.goals, 2)
+    assert not np.allclose(st.resid, _blocks_by_loops(prob, obs, st), rtol=1e-10, atol=1e-12)
+    monkeypatch.setattr(O, "build_F", real_build_F)
+
+    real_res = O.residuals
+    monkeypatch.setattr(O, "residuals", lambda *a: real_res(*a)[[0, 2, 1, 3]])
+    prob = O.Problem(sc.n_time, sc.t_f, obs.shape[0], PARAMS)
+    st = O.solve(prob, sc.ego, obs, sc.goals, 2)
+    assert not np.allclose(st.resid, _blocks_by_loops(prob, obs, st), rtol=1e-10, atol=1e-12)
+
+
+def test_all_three_multiplier_updates_by_explicit_loops():
+    """Eq. 23 for lambda_x and lambda_y and eq. 24 (read with the residual oriented
+    as in eq. 23) for lambda_psi: the increment of one iteration equals
+    rho * sum_i (row of F_ax at t_i) * (g - F_ax c)_i, per axis, and
+    rho * sum_i P_i (atan2(y'_i, x'_i) - psi_i), summed sample by sample."""
+    sc, obs = _moving_obstacle_scene()
+    prob = O.Problem(sc.n_time, sc.t_f, obs.shape[0], PARAMS)
+    st0 = O.solve(prob, sc.ego, obs, sc.goals, 3)
+    init = {k: getattr(st0, k) for k in ("c_x", "c_y", "c_psi", "lam_x", "lam_y", "lam_psi")}
+    st1 = O.solve(prob, sc.ego, obs, sc.goals, 1, init=init)
+    n, m, a, b, rho = prob.n, prob.m, prob.a, prob.b, prob.rho
+    B = st1.c_x.shape[1]
+    inc = np.zeros((3, 11, B))
+    for l in range(B):
+        for i in range(n):
+            ti = i * prob.t_f / (n - 1)
+            P, Pd, Pdd = prob.P[i], prob.Pd[i], prob.Pdd[i]
+            x, y = P @ st1.c_x[:, l], P @ st1.c_y[:, l]
+            xd, yd = Pd @ st1.c_x[:, l], Pd @ st1.c_y[:, l]
+            xdd, ydd = Pdd @ st1.c_x[:, l], Pdd @ st1.c_y[:, l]
+            psi = P @ st1.c_psi[:, l]
+            for j in range(m):
+                dx = x - (obs[j, 0] + obs[j, 2] * ti)
+                dy = y - (obs[j, 1] + obs[j, 3] * ti)
+                al = math.atan2(a * dy, b * dx)
+                d = max(1.0, math.sqrt((dx / a) ** 2 + (dy / b) ** 2))
+                inc[0, :, l] += P * (a * d * math.cos(al) - dx)
+                inc[1, :, l] += P * (b * d * math.sin(al) - dy)
+            h = math.hypot(xdd, ydd)
+            d_a = min(prob.a_max, h)
+            al_a = math.atan2(ydd, xdd)
+            inc[0, :, l] += Pdd * (d_a * math.cos(al_a) - xdd)
+            inc[1, :, l] += Pdd * (d_a * math.sin(al_a) - ydd)
+            v = min(max(math.hypot(xd, yd), prob.v_min), prob.v_max)
+            inc[0, :, l] += Pd * (v * math.cos(psi) - xd)
+            inc[1, :, l] += Pd * (v * math.sin(psi) - yd)
+            inc[2, :, l] += P * (math.atan2(yd, xd) - psi)
+    got = np.stack([st1.lam_x - st0.lam_x, st1.lam_y - st0.lam_y, st1.lam_psi - st0.lam_psi])
+    assert np.allclose(got, rho * inc, rtol=1e-9, atol=1e-9)
+    assert np.max(np.abs(inc[2])) > 1e-3  # the heading increment is exercised
+
+
+def _p8_seed(seed):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        sc = S.workload_small(seed).scenes[0]
+        prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+        st = O.solve(prob, sc.ego, sc.obs, sc.goals, 100, record=True)
+        # the best performing trajectory (Fig. 3a): lowest eq. 25 cost; the heading
+        # filter is not applied here, so every seed has one
+        v = np.hypot(prob.Pd @ st.c_x, prob.Pd @ st.c_y)
+        best = int(np.argmin(np.sum((v - float(sc.ego[2])) ** 2, axis=0)))
+        h = st.hist[:, :3, best]
+        return seed, bool(np.all(np.isfinite(st.hist))), float(h[0].max()), float(h[-1].max())
+
+
+def test_stopping_residual_of_best_goal_falls_on_every_config1_seed():
+    """Convergence invariant (Sec. IV, Fig. 3a: the residual of the best performing
+    trajectory falls over the iterations): on every 11-goal scene of seeds 0-99,
+    max(r_obs, r_acc, r_nh) of the meta-cost-best goal after 100 iterations is
+    below its value after the first (or both are at rounding level: a straight-lane
+    goal with no obstacle in reach is a fixed point from the start). The printed
+    sign of eq. 24 and a flipped sign of eq. 23, planted in the oracle, fail this
+    on all 100 seeds."""
+    from multiprocessing import get_context
+    with get_context("spawn").Pool(min(8, os.cpu_count() or 1)) as pool:
+        rows = pool.map(_p8_seed, range(100))
+    bad = [r for r in rows if not (r[1] and (r[3] < r[2] or max(r[2], r[3]) <= 1e-9))]
+    assert not bad, bad
+
+
+def _planted_oracle(old, new):
+    """A copy of the oracle module with one line of its arithmetic replaced (a
+    mistake planted on the CPU, to show that a pin rejects it)."""
+    path = os.path.join(os.path.dirname(HERE), "oracle", "traj_oracle.py")
+    with open(path) as f:
+        src = f.read()
+    assert src.count(old) == 1
+    ns = {"__name__": "planted_oracle"}
+    exec(compile(src.replace(old, new), "planted_oracle", "exec"), ns)
+    return ns
+
+
+@pytest.mark.parametrize("old,new", [
+    ("st.lam_psi = st.lam_psi - rho * prob.P.T @ (prob.P @ st.c_psi - st.theta)",
+     "st.lam_psi = st.lam_psi + rho * prob.P.T @ (prob.P @ st.c_psi - st.theta)"),
+    ("lam_xy = lam_xy - rho * prob.F.T @ (prob.F @ c - g)",
+     "lam_xy = lam_xy + rho * prob.F.T @ (prob.F @ c - g)")])
+def test_stopping_residual_pin_rejects_planted_multiplier_signs(old, new):
+    from threadpoolctl import threadpool_limits
+    ns = _planted_oracle(old, new)
+    with threadpool_limits(1):
+        _check_planted(ns)
+
+
+def _check_planted(ns):
+    for seed in range(6):
+        sc = S.workload_small(seed).scenes[0]
+        prob = ns["Problem"](sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+        with np.errstate(all="ignore"):
+            st = ns["solve"](prob, sc.ego, sc.obs, sc.goals, 100, record=True)
+            v = np.hypot(prob.Pd @ st.c_x, prob.Pd @ st.c_y)
+            best = int(np.nanargmin(np.sum((v - float(sc.ego[2])) ** 2, axis=0)))
+        h = st.hist[:, :3, best]
+        assert not (np.all(np.isfinite(st.hist)) and h[-1].max() < h[0].max()), seed
