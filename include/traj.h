@@ -165,6 +165,28 @@ int traj_solve_batch(void *handle, const traj_batch *batch, traj_state *state, i
                      uint32_t flags, void *stream);
 
 /*
+ * traj_solve_batch_noalloc -- traj_solve_batch for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): a group-kernel solve takes its work list from a scratch
+ * array that the library holds in device memory (one per GPU, reserved when the
+ * library is loaded, kept until the process ends) instead of state->work, which
+ * is ignored. Everything else (arguments, flags, results, errors) is as
+ * traj_solve_batch; the wave and MFMA kernels use no scratch. The call makes no
+ * allocation of any kind.
+ *   Limit: the work list (traj_work_ints for the batch and the handle's group
+ *   size) must fit in TRAJ_NOALLOC_WORK_INTS int32 (2 MiB), e.g. 118,830 goals
+ *   in 512 scenes at every group size; larger batches get TRAJ_E_INVAL.
+ *   The current device must be the one the handle was set up on (TRAJ_E_INVAL).
+ *   Every call on a GPU shares that GPU's scratch: two calls whose work overlaps
+ *   on one GPU (other streams, other threads, other handles) race and give wrong
+ *   results. Each call rebuilds the list before reading it, so nothing carries
+ *   over from the previous call.
+ */
+#define TRAJ_NOALLOC_WORK_INTS 524288
+int traj_solve_batch_noalloc(void *handle, const traj_batch *batch, traj_state *state, int iters, float tol,
+                             uint32_t flags, void *stream);
+
+/*
  * traj_score -- meta-cost per goal (eq. 25 or 26, v(t) = |(x'(t), y'(t))| of the
  * final coefficients) with the heading post-filter (cost = +inf when
  * max_t |psi(t)| > psi_max, Sec. III assumption 2) and, if mc->clear_min > 0,

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,6 +56,38 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(TRAJ_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace
+
+// Library-owned scratch of traj_solve_batch_noalloc: the group kernel's work list
+// (claim counter, cost-sorted goal groups, goal order per scene, solved goals per
+// scene). Every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel: it uses the device address
+// that resolve_scratch() takes once per device (at setup) and keeps.
+static __device__ __align__(256) int32_t scratch[TRAJ_NOALLOC_WORK_INTS];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, which must be the current device.
+// Resolved on the first call for that device and kept.
+hipError_t resolve_scratch(int dev, int32_t** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 struct Handle {
   traj_params p;
   std::vector<ShapeDesc> shapes;
@@ -65,6 +98,8 @@ struct Handle {
   size_t table_floats = 0;
   traj_tile tile = {(int32_t)TRAJ_KERNEL_WAVE, 16, 1, 1};
   int resident_blocks[2] = {0, 0};  // group kernel workgroups resident at once, per precision mode
+  int device = -1;                  // the device current at setup (tables and scratch live there)
+  int32_t* scratch = nullptr;       // that device's address of the no-allocation scratch
 };
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
@@ -93,7 +128,7 @@ int check_batch(const Handle* h, const traj_batch* b) {
 }
 
 int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
-               void* stream, bool reuse_order);
+               void* stream, bool reuse_order, int32_t* static_work = nullptr);
 int score_impl(Handle* h, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
                int32_t* best, void* stream, const int32_t* skip = nullptr,
                const traj::ConvergeCheck* check = nullptr);
@@ -170,6 +205,11 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
     }
     h->resident_blocks[mode] = cus * (per_cu > 0 ? per_cu : 1);
   }
+  h->device = dev;
+  if ((e = resolve_scratch(dev, &h->scratch)) != hipSuccess) {
+    traj_destroy(h);
+    return hip_fail(e, "traj_setup: address of the library scratch");
+  }
   // the MFMA kernel's dynamic LDS for this handle's shapes (larger handles are
   // refused at dispatch)
   if ((e = traj::mfma_reserve_smem(traj::mfma_smem_bytes(h->max_n, h->max_m))) != hipSuccess) {
@@ -194,6 +234,21 @@ int traj_solve_batch(void* handle, const traj_batch* batch, traj_state* state, i
                      void* stream) {
   g_err.clear();
   return solve_impl((Handle*)handle, batch, state, iters, tol, flags, stream, false);
+}
+
+int traj_solve_batch_noalloc(void* handle, const traj_batch* batch, traj_state* state, int iters, float tol,
+                             uint32_t flags, void* stream) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
+  int cur = -1;
+  const hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "traj_solve_batch_noalloc: current device");
+  if (cur != h->device)
+    return fail(TRAJ_E_INVAL, "traj_solve_batch_noalloc: current device %d is not the handle's device %d", cur,
+                h->device);
+  if (h->scratch == nullptr) return fail(TRAJ_E_HIP, "traj_solve_batch_noalloc: library scratch not resolved");
+  return solve_impl(h, batch, state, iters, tol, flags, stream, false, h->scratch);
 }
 
 int traj_score(void* handle, const traj_batch* batch, const traj_state* state, const traj_metacost* mc, float* cost,
@@ -242,8 +297,10 @@ int traj_converge(void* handle, const traj_batch* batch, traj_state* state, cons
 
 namespace {
 
+// static_work: the library scratch (traj_solve_batch_noalloc), used instead of
+// state->work by a group-kernel solve; NULL for traj_solve_batch.
 int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters, float tol, uint32_t flags,
-               void* stream, bool reuse_order) {
+               void* stream, bool reuse_order, int32_t* static_work) {
   if (h == nullptr) return fail(TRAJ_E_INVAL, "handle is NULL");
   int rc = check_batch(h, batch);
   if (rc != TRAJ_OK) return rc;
@@ -266,11 +323,20 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
     return fail(TRAJ_E_INVAL, "TRAJ_WARM_FALLBACK runs on the group kernel only");
   if (batch->n_goals == 0) return TRAJ_OK;
   if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
+  int32_t* work = state->work;
   if (kernel == TRAJ_KERNEL_GROUP) {
     const int64_t need = traj::group_work_ints(batch->n_scenes, batch->n_goals, h->tile.group);
-    if (state->work == nullptr || state->work_ints < need)
+    if (static_work != nullptr) {
+      if (need > (int64_t)TRAJ_NOALLOC_WORK_INTS)
+        return fail(TRAJ_E_INVAL,
+                    "traj_solve_batch_noalloc: the group kernel's work list for %d scenes and %d goals (group "
+                    "size %d) needs %lld int32, more than the library scratch of %d",
+                    batch->n_scenes, batch->n_goals, h->tile.group, (long long)need, TRAJ_NOALLOC_WORK_INTS);
+      work = static_work;
+    } else if (state->work == nullptr || state->work_ints < need) {
       return fail(TRAJ_E_INVAL, "the group kernel needs state.work with %lld int32 (got %lld)", (long long)need,
                   (long long)(state->work == nullptr ? 0 : state->work_ints));
+    }
   }
   traj::SolveArgs a;
   a.goal_off = batch->goal_off;
@@ -298,7 +364,7 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
   hipError_t e;
   if (kernel == TRAJ_KERNEL_GROUP) {
     e = traj::launch_solve_group(a, mode, h->tile.group, h->tile.persistent != 0, h->resident_blocks[mode],
-                                 state->work, reuse_order, (hipStream_t)stream);
+                                 work, reuse_order, (hipStream_t)stream);
   } else if (kernel == TRAJ_KERNEL_MFMA) {
     const size_t need = traj::mfma_smem_bytes(h->max_n, h->max_m);
     if (need > traj::MFMA_SMEM_LIMIT)

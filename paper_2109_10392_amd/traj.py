@@ -78,7 +78,7 @@ MLP_EXPORTS = ("traj_mlp_param_count", "traj_mlp_sync_bf16", "traj_features", "t
                "traj_mlp_backward", "traj_mlp_adam", "traj_colstats", "traj_state_rows", "traj_rows_state",
                "traj_gemm_bf16")
 
-EXPORTS = ("traj_setup", "traj_solve_batch", "traj_score", "traj_destroy", "traj_last_error",
+EXPORTS = ("traj_setup", "traj_solve_batch", "traj_solve_batch_noalloc", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
            "traj_work_ints", "traj_converge", "traj_debug_atan2", "traj_controls")
 
@@ -96,6 +96,8 @@ def lib():
     vp, i32, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
     L.traj_setup.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Shape), i32, vp, ctypes.POINTER(vp)]
     L.traj_solve_batch.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), i32, f32, ctypes.c_uint32, vp]
+    L.traj_solve_batch_noalloc.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), i32, f32,
+                                           ctypes.c_uint32, vp]
     L.traj_score.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), ctypes.POINTER(MetaC), vp, vp, vp]
     L.traj_destroy.argtypes = [vp]
     L.traj_last_error.restype = ctypes.c_char_p
@@ -265,6 +267,17 @@ class Solver:
         flags = self._flags(from_state, fallback, precision, kernel)
         _check(lib().traj_solve_batch(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
                                       flags, _stream(stream)))
+
+    def solve_noalloc(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,
+                      from_state: bool = False, precision: str = "fp32", kernel: str = "auto", stream=None,
+                      fallback: bool = False):
+        """solve() through traj_solve_batch_noalloc: the group kernel's work list lives
+        in the library's own device scratch (state.work is not used)."""
+        b = batch.c_struct()
+        s = state.c_struct()
+        flags = self._flags(from_state, fallback, precision, kernel)
+        _check(lib().traj_solve_batch_noalloc(self.handle, ctypes.byref(b), ctypes.byref(s), int(iters), float(tol),
+                                              flags, _stream(stream)))
 
     def set_tile(self, kernel: str, group: int = 16, persistent: bool = True, waves: int = 1):
         t = TileC(_KERNELS[kernel], int(group), 1 if persistent else 0, int(waves))
