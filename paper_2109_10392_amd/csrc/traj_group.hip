@@ -413,18 +413,40 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   f4 cx = zero, cy = zero, cp = zero, lx = zero, ly = zero, lp = zero;
   const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
   Particular P;
-  particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, cold, cx, cy);
-  // the FP64 particular parts wait in LDS between applies ([axis][r][lane])
+  particular<MODE>(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, cold, cx, cy);
+  // the particular parts of the x/y step wait in LDS between applies ([axis][r][lane];
+  // FP64 in the FP32 form, FP32 in the split form)
+  float* sc0f = reinterpret_cast<float*>(sc0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    sc0[(0 * 4 + r) * WAVE + lane] = P.c0xd[r];
-    sc0[(1 * 4 + r) * WAVE + lane] = P.c0yd[r];
+    if constexpr (MODE == TRAJ_MODE_FP32) {
+      sc0[(0 * 4 + r) * WAVE + lane] = P.c0xd[r];
+      sc0[(1 * 4 + r) * WAVE + lane] = P.c0yd[r];
+    } else {
+      sc0f[(0 * 4 + r) * WAVE + lane] = P.c0x[r];
+      sc0f[(1 * 4 + r) * WAVE + lane] = P.c0y[r];
+    }
   }
   auto c0d = [&](int axis) {
     d4 v;
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = sc0[(axis * 4 + r) * WAVE + lane];
     return v;
+  };
+  auto c0f = [&](int axis) {
+    f4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = sc0f[(axis * 4 + r) * WAVE + lane];
+    return v;
+  };
+  // the x/y step (eq. 18) and heading step (eq. 20) of one axis in the kernel's precision
+  auto step_xy = [&](int axis, const f4& c, const f4& r) {
+    if constexpr (MODE == TRAJ_MODE_FP32) return apply_xy(xy_ops(axis), c0d(axis), c, r);
+    else return apply_xy_split3(T + opaque_offset(), n, axis, j, q, c0f(axis), c, r);
+  };
+  auto step_psi = [&](const f4& r) {
+    if constexpr (MODE == TRAJ_MODE_FP32) return apply_psi(psi_ops(), P.c0p, r);
+    else return apply_psi_split3(T + opaque_offset(), n, j, q, P.c0p, r);
   };
   if (!cold) {
 #pragma unroll
@@ -575,16 +597,16 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   // d), (alpha_a, d_a); no multiplier is updated here
   auto start = [&](bool cold_start) {
     const f4 W = heading_sweep();
-    if (cold_start) cp = apply_psi(psi_ops(), P.c0p, rho * W + lp);
+    if (cold_start) cp = step_psi(rho * W + lp);
     projection_sweep(ux, uy, E);
   };
   auto iteration = [&]() {
     // x/y step (eq. 12 through eq. 18)
-    cx = apply_xy(xy_ops(0), c0d(0), cx, rho * ux + lx);
-    cy = apply_xy(xy_ops(1), c0d(1), cy, rho * uy + ly);
+    cx = step_xy(0, cx, rho * ux + lx);
+    cy = step_xy(1, cy, rho * uy + ly);
     // heading step (eq. 13 through eq. 20)
     const f4 W = heading_sweep();
-    cp = apply_psi(psi_ops(), P.c0p, rho * W + lp);
+    cp = step_psi(rho * W + lp);
     // v, (alpha, d), (alpha_a, d_a), then the multipliers (eqs. 23, 24)
     projection_sweep(ux, uy, E);
     lx = lx + rho * ux;
@@ -638,7 +660,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     ly = zero;
     lp = zero;
     cp = zero;
-    particular(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, true, cx, cy);
+    particular<MODE>(T, T64, n, A.ego + 8 * scene, A.goal + 2 * g, q, P, true, cx, cy);
     start(true);
     iteration();
     const float r_cold = worst_resid();
@@ -681,7 +703,8 @@ template <int MODE>
 __global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A, GroupArgs L) {
   __shared__ float4 sobs[GROUP_WAVES][MAX_OBS];           // each wave's current scene's obstacles (scaled)
   __shared__ float4 sth[GROUP_WAVES][MAX_TILES * WAVE];    // each wave's theta at its lanes' samples
-  __shared__ double sc0[GROUP_WAVES][2 * 4 * WAVE];        // each wave's FP64 particular parts (x, y)
+  __shared__ double sc0[GROUP_WAVES][2 * 4 * WAVE];  // each wave's particular parts of the x/y step (FP64 in
+                                                     // the FP32 form, FP32 in the split form)
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
   const int n_items = L.header[1];
   int idx = L.persistent ? claim(L.header) : (int)blockIdx.x * GROUP_WAVES + wv;

@@ -295,18 +295,28 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
   const float bp[NP] = {e[6], e[7], 0.f, 0.f};
   const float* Bt = T + tab_bnd(n);
+  // the x/y parts in FP64 (FP32 form) or FP32 (split form, no FP64 arithmetic)
   d4 c0xd = {0.0, 0.0, 0.0, 0.0}, c0yd = {0.0, 0.0, 0.0, 0.0};
   f4 c0p = {0.f, 0.f, 0.f, 0.f};
+  f4 c0x = c0p, c0y = c0p;
   f4 cx = c0p, cy = c0p, cp = c0p, lx = c0p, ly = c0p, lp = c0p;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int k = 4 * q + r;
     if (k < NC) {
-      double sx = 0.0, sy = 0.0;
-      for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
-      for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
-      c0xd[r] = sx;
-      c0yd[r] = sy;
+      if constexpr (MODE == TRAJ_MODE_FP32) {
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
+        for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
+        c0xd[r] = sx;
+        c0yd[r] = sy;
+      } else {
+        float sx = 0.f, sy = 0.f;
+        for (int i = 0; i < NX; ++i) sx = fmaf(Bt[BND_MBX + k * NX + i], bx[i], sx);
+        for (int i = 0; i < NY; ++i) sy = fmaf(Bt[BND_MBY + k * NY + i], by[i], sy);
+        c0x[r] = sx;
+        c0y[r] = sy;
+      }
       float sp = 0.f;
       for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
       c0p[r] = sp;
@@ -440,7 +450,10 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   {
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
-    if (cold) cp = apply_psi(O.psi, c0p, rho * W_ + lp);
+    if (cold) {
+      if constexpr (MODE == TRAJ_MODE_FP32) cp = apply_psi(O.psi, c0p, rho * W_ + lp);
+      else cp = apply_psi_split3(T, n, j, q, c0p, rho * W_ + lp);
+    }
     project(xd, yd, th);
     ep = zero;  // the start has no pending heading multiplier step
   }
@@ -452,17 +465,23 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
       // an offset the compiler cannot see through keeps the loop-invariant loads in the loop
       int opaque = 0;
       asm volatile("" : "+v"(opaque));
-      XYOps o;
-      load_xy_ops(o, T64 + opaque, 0, j, q);
-      cx = apply_xy(o, c0xd, cx, rho * ux + lx);
-      load_xy_ops(o, T64 + opaque, 1, j, q);
-      cy = apply_xy(o, c0yd, cy, rho * uy + ly);
+      if constexpr (MODE == TRAJ_MODE_FP32) {
+        XYOps o;
+        load_xy_ops(o, T64 + opaque, 0, j, q);
+        cx = apply_xy(o, c0xd, cx, rho * ux + lx);
+        load_xy_ops(o, T64 + opaque, 1, j, q);
+        cy = apply_xy(o, c0yd, cy, rho * uy + ly);
+      } else {
+        cx = apply_xy_split3(T + opaque, n, 0, j, q, c0x, cx, rho * ux + lx);
+        cy = apply_xy_split3(T + opaque, n, 1, j, q, c0y, cy, rho * uy + ly);
+      }
     }
     // pending heading multiplier (eq. 24) and heading step (eq. 13 through eq. 20)
     f4 xd, yd, th, W_, E_;
     heading(xd, yd, th, W_, E_);
     lp = lp + rho * E_;
-    cp = apply_psi(O.psi, c0p, rho * W_ + lp);
+    if constexpr (MODE == TRAJ_MODE_FP32) cp = apply_psi(O.psi, c0p, rho * W_ + lp);
+    else cp = apply_psi_split3(T, n, j, q, c0p, rho * W_ + lp);
     // v, (alpha, d), (alpha_a, d_a) and u~ (eqs. 14-16, 21, 22)
     project(xd, yd, th);
     // multipliers of the x/y block (eq. 23)

@@ -14,7 +14,12 @@
 //           operators stay FP64.
 //   BF16x3: v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo (bf16 each):
 //           hi*hi + lo*hi + hi*lo in two instructions (K = 32 holds hi and lo of
-//           16 K values), FP32 accumulation, for every contraction and apply.
+//           16 K values), FP32 accumulation, for the basis evaluations and the x/y
+//           contractions; the heading contraction on v_mfma_f32_16x16x4_f32; the
+//           x/y and heading applies (inverse x right-hand side, eqs. 18, 20) in a
+//           three-way split h + m + l (bf16 each, exact for FP32 values) with the
+//           six products of order >= 2^-16 in three instructions. No FP64
+//           arithmetic: FP64 stays in forming and inverting the KKT matrices.
 #pragma once
 #include "traj_device.h"
 
@@ -116,14 +121,83 @@ __device__ __forceinline__ f4 contract(const Operand<MODE>& a, const f4& s, f4 a
   return acc;
 }
 
-// Operators of the x/y and heading applies (rows of the lane's column).
+// Three-way split of an FP32 value into bf16 parts, x = h + m + l: each part takes
+// the next 8 significant bits of the remainder (the subtractions are exact).
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+// acc + A v for one 16 x 16 operator in the three-way split: lane (j, q) holds
+// a[e] = A[row j][k = 4 q + e] and its column's values v[e] = v[k = 4 q + e]. K slot
+// 8 q + e carries k = 4 q + e and slot 8 q + 4 + e the same k again, so the three
+// instructions form h(A) (h(v) + m(v)), m(A) (h(v) + m(v)) and l(A) h(v) + h(A) l(v):
+// every product of order >= 2^-16 of the leading one, FP32 accumulation, smallest
+// terms first.
+__device__ __forceinline__ f4 mv_split3(const float (&a)[4], const f4& v, f4 acc) {
+  bf8 vhm, vhl, a_h, a_m, a_lh;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    __bf16 h, m, l;
+    split3(v[e], h, m, l);
+    vhm[e] = h;
+    vhm[e + 4] = m;
+    vhl[e] = h;
+    vhl[e + 4] = l;
+    split3(a[e], h, m, l);
+    a_h[e] = h;
+    a_h[e + 4] = h;
+    a_m[e] = m;
+    a_m[e + 4] = m;
+    a_lh[e] = l;
+    a_lh[e + 4] = h;
+  }
+  acc = mmabf(a_lh, vhl, acc);
+  acc = mmabf(a_m, vhm, acc);
+  return mmabf(a_h, vhm, acc);
+}
+
+// Row j of an NC x NC operator of the FP32 table at the lane's K values 4 q + e
+// (zero outside the NC x NC block).
+__device__ __forceinline__ void load_row4(const float* __restrict__ T, int n, int sq, int j, int q, float (&a)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * q + e;
+    a[e] = (j < NC && k < NC) ? T[tab_square(n, sq) + j * NC + k] : 0.f;
+  }
+}
+
+// The split form's x/y step for one axis: c0 + MG c + M r (eq. 18), three-way split.
+__device__ __forceinline__ f4 apply_xy_split3(const float* __restrict__ T, int n, int axis, int j, int q,
+                                              const f4& c0, const f4& c, const f4& r) {
+  float a[4];
+  load_row4(T, n, axis == 0 ? SQ_MX : SQ_MY, j, q, a);
+  f4 acc = mv_split3(a, r, c0);
+  load_row4(T, n, axis == 0 ? SQ_MGX : SQ_MGY, j, q, a);
+  return mv_split3(a, c, acc);
+}
+
+// The split form's heading step: c0p + M_psi r (eq. 20), three-way split.
+__device__ __forceinline__ f4 apply_psi_split3(const float* __restrict__ T, int n, int j, int q, const f4& c0p,
+                                               const f4& r) {
+  float a[4];
+  load_row4(T, n, SQ_MP, j, q, a);
+  return mv_split3(a, r, c0p);
+}
+
+// Operators of the FP32 form's x/y and heading applies (rows of the lane's column).
 //
-// The x/y step's constant operators are FP64 in both forms: they act on
-// coefficients of hundreds of metres, and their rounding is integrated by the
-// multipliers (eqs. 23, 24) over the iterations. The heading operator (eq. 20) is
-// FP32 in both forms: its entries reach ~70 and its row sums ~200 while its
-// products cancel to angles of tenths of a radian, so a split-BF16 product (about
-// 16 significant bits) would leave errors of ~1e-3 rad in the coefficients.
+// The FP32 form keeps the x/y step's constant operators in FP64: they act on
+// coefficients of hundreds of metres with products that cancel, their rounding
+// is integrated by the multipliers (eqs. 23, 24) over the iterations, and with
+// 50 obstacles an FP32 apply leaves coefficient errors of 2-4e-4 against the
+// oracle. The split form, held to a decade looser gate, uses the three-way split
+// above (FP32-level products) for these applies. A two-way split (about 16
+// significant bits) is too coarse for both applies: the heading operator's
+// entries reach ~70 and its row sums ~200 while its products cancel to angles of
+// tenths of a radian.
 struct XYOps {
   double mg[4], m[4];  // rows permuted for the f64 output layout
 };
@@ -222,11 +296,14 @@ __device__ __forceinline__ float sum_rows(float v) {
 // Boundary values (eq. 8b) of a goal and the particular parts M_b b of its three
 // steps at the lane's coefficient rows 4q + r; with cold, also the boundary-only
 // minimum-acceleration start.
+// FP32 form: the x/y parts in FP64 (c0xd, c0yd); split form: in FP32 (c0x, c0y).
 struct Particular {
   d4 c0xd, c0yd;
+  f4 c0x, c0y;
   f4 c0p;
 };
 
+template <int MODE>
 __device__ __forceinline__ void particular(const float* __restrict__ T, const double* __restrict__ T64, int n,
                                            const float* e, const float* gl, int q, Particular& P, bool cold, f4& cx,
                                            f4& cy) {
@@ -239,13 +316,23 @@ __device__ __forceinline__ void particular(const float* __restrict__ T, const do
     const int k = 4 * q + r;
     P.c0xd[r] = 0.0;
     P.c0yd[r] = 0.0;
+    P.c0x[r] = 0.f;
+    P.c0y[r] = 0.f;
     P.c0p[r] = 0.f;
     if (k < NC) {
-      double sx = 0.0, sy = 0.0;
-      for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
-      for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
-      P.c0xd[r] = sx;
-      P.c0yd[r] = sy;
+      if constexpr (MODE == TRAJ_MODE_FP32) {
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < NX; ++i) sx = fma(T64[T64_MBX + k * NX + i], (double)bx[i], sx);
+        for (int i = 0; i < NY; ++i) sy = fma(T64[T64_MBY + k * NY + i], (double)by[i], sy);
+        P.c0xd[r] = sx;
+        P.c0yd[r] = sy;
+      } else {
+        float sx = 0.f, sy = 0.f;
+        for (int i = 0; i < NX; ++i) sx = fmaf(Bt[BND_MBX + k * NX + i], bx[i], sx);
+        for (int i = 0; i < NY; ++i) sy = fmaf(Bt[BND_MBY + k * NY + i], by[i], sy);
+        P.c0x[r] = sx;
+        P.c0y[r] = sy;
+      }
       float sp = 0.f;
       for (int i = 0; i < NP; ++i) sp = fmaf(Bt[BND_MBP + k * NP + i], bp[i], sp);
       P.c0p[r] = sp;
