@@ -31,8 +31,8 @@
 //   is c_new = (M rho F_ax^T F_ax) c + M (rho u~ + lam) + M_b b.
 // The contractions over time (P^T s, P^T theta) are lane-parallel products
 // followed by a reduce-scatter across the wave (permlane swaps + DPP); the
-// 11x11 applies run one output row per lane with the input broadcast through
-// scalar registers.
+// 11x11 applies run one output row per lane, their inputs and outputs broadcast
+// through a per-wave LDS slot (one write by the home lanes, vector reads by all).
 #include "traj_device.h"
 
 namespace traj {
@@ -70,10 +70,47 @@ __device__ __forceinline__ float pair_sum(float v, float* ex, int& buf) {
   return r;
 }
 
-// Basis rows of the lane's samples (slot s holds sample lane + 64 s).
+// Wave-local LDS exchange. Values written by some lanes of a wave and read by
+// others of the same wave: the fences and the wave barrier keep the compiler from
+// moving the reads above the writes (the hardware runs one wave's LDS accesses
+// in order).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The home lanes' values of one coefficient vector: lane 2k (k < NC) holds value k
+// of the lower set, lane 32 + 2k value k of the upper set. They are written to the
+// wave's slot (lower set at [0, 16), upper set at [16, 32)).
+__device__ __forceinline__ void put_home(float v, float* slot) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int k = (lane & 31) >> 1;
+  if ((lane & 1) == 0 && k < NC) slot[(lane >> 5) * 16 + k] = v;
+}
+
+// The NC values at slot[0, NC) into registers (every lane reads the same words).
+__device__ __forceinline__ void get_vec(const float* slot, float (&v)[NC]) {
+  const float4* s4 = reinterpret_cast<const float4*>(slot);
+  const float4 a = s4[0], b = s4[1], c = s4[2];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  v[8] = c.x; v[9] = c.y; v[10] = c.z;
+}
+
+// Samples of a goal's WPG waves: wave w holds span = ceil(n / WPG) consecutive
+// samples starting at w span, slot s the 64 of them from w span + 64 s (so the
+// waves' shares, and their obstacle work, stay balanced).
+__host__ __device__ inline int wave_span(int n, int wpg) { return (n + wpg - 1) / wpg; }
+__host__ __device__ inline int slot_start(int n, int wpg, int w, int s) { return w * wave_span(n, wpg) + WAVE * s; }
+
+// Basis rows of the lane's samples, their times, and each slot's culling boxes of
+// the lane's obstacle (one per row of 16 samples; loop-invariant, held in registers).
 template <int S>
 struct Lane {
   float P[S][NC], Pd[S][NC], Pdd[S][NC];
+  float tm[S];
+  float4 box[S][WAVE / 16];
   bool val[S];
 };
 
@@ -117,7 +154,7 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
                                             const float4* __restrict__ box,
                                             const float (&cx)[NC], const float (&cy)[NC], const float (&cp)[NC],
                                             const float (&xd)[S], const float (&yd)[S], const float (&th)[S],
-                                            float (&ep)[S], float (&part)[32]) {
+                                            float (&ep)[S], float (&part)[32], float* bslot) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = (threadIdx.x >> 6) % WPG;
 #pragma unroll
@@ -150,18 +187,18 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     const float inf = __builtin_inff();
     const float xlo = row_min(L.val[s] ? X : inf), xhi = row_max(L.val[s] ? X : -inf);
     const float ylo = row_min(L.val[s] ? Y : inf), yhi = row_max(L.val[s] ? Y : -inf);
+    // each row's box to every lane through the wave's LDS slot
+    if ((lane & 15) == 0) reinterpret_cast<float4*>(bslot)[lane >> 4] = make_float4(xlo, xhi, ylo, yhi);
+    wave_sync_lds();
     bool hit = false;
 #pragma unroll
     for (int rw = 0; rw < WAVE / 16; ++rw) {
-      const float rxlo = rdlane(xlo, 16 * rw), rxhi = rdlane(xhi, 16 * rw);
-      const float rylo = rdlane(ylo, 16 * rw), ryhi = rdlane(yhi, 16 * rw);
-      if (lane < G.m) {
-        const float4 bx = box[(gs * (WAVE / 16) + rw) * MAX_OBS + lane];
-        hit = hit || ((rxhi > bx.x) && (rxlo < bx.y) && (ryhi > bx.z) && (rylo < bx.w));
-      }
+      const float4 rb = reinterpret_cast<const float4*>(bslot)[rw];
+      const float4 bx = L.box[s][rw];
+      hit = hit || ((rb.y > bx.x) && (rb.x < bx.y) && (rb.w > bx.z) && (rb.z < bx.w));
     }
-    unsigned long long cand = __ballot(hit);
-    const float tm = (float)(lane + WAVE * gs) * G.dt;
+    unsigned long long cand = __ballot(hit && lane < G.m);
+    const float tm = L.tm[s];
     float Sx = 0.f, Sy = 0.f, ro = 0.f;
     while (cand) {
       // up to four candidates per round, their LDS reads issued together
@@ -183,15 +220,14 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (qq[u] < 1.f) {
-            if (qq[u] > 0.f) {
-              const float f = rsqrtf(qq[u]) - 1.f;
-              Sx = fmaf(tx[u], f, Sx);
-              Sy = fmaf(ty[u], f, Sy);
-              ro = fmaf(fmaf(G.a2 * tx[u], tx[u], G.b2 * ty[u] * ty[u]), f * f, ro);
-            } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
-              Sx += 1.f;
-              ro += G.a2;
-            }
+            // inside: d/du - 1 = 1/du - 1 with du = sqrt(q) (q is a normal number or 0
+            // here, where the hardware reciprocal square root is the library's); on the
+            // obstacle centre alpha = atan2(+0, +0) = 0 and d = 1
+            const bool centre = !(qq[u] > 0.f);
+            const float f = __builtin_amdgcn_rsqf(qq[u]) - 1.f;
+            Sx = centre ? Sx + 1.f : fmaf(tx[u], f, Sx);
+            Sy = centre ? Sy : fmaf(ty[u], f, Sy);
+            ro = centre ? ro + G.a2 : fmaf(fmaf(G.a2 * tx[u], tx[u], G.b2 * ty[u] * ty[u]), f * f, ro);
           }
         }
       }
@@ -212,10 +248,15 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
   }
 }
 
+// Per-wave LDS slots of solve_goal (floats): coefficient broadcast (x at [0, 16),
+// y at [16, 32)), apply inputs (same layout), heading step input and output, the
+// row boxes of the obstacle culling.
+constexpr int SLOT_C = 0, SLOT_R = 32, SLOT_P = 64, SLOT_Q = 80, SLOT_B = 96, SLOT_FLOATS = 112;
+
 template <int S, int WPG>
 __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float* __restrict__ T,
-                           const float4* __restrict__ sobs, const float4* __restrict__ box,
-                           const double* __restrict__ apply64, float* ex, int scene, int g) {
+                           const float4* __restrict__ sobs, const float4* __restrict__ box, float* ex, float* slots,
+                           int scene, int g) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = (threadIdx.x >> 6) % WPG;
   int buf = 0;
@@ -241,11 +282,16 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   const int n = G.n;
 
   Lane<S> L;
+  const int span = wave_span(n, WPG);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int t = lane + WAVE * (WPG * s + wv);
-    L.val[s] = t < n;
+    const int t = slot_start(n, WPG, wv, s) + lane;
+    L.val[s] = WAVE * s + lane < span && t < n;
     const int tc = L.val[s] ? t : 0;
+    L.tm[s] = (float)t * G.dt;
+#pragma unroll
+    for (int rw = 0; rw < WAVE / 16; ++rw)
+      L.box[s][rw] = box[((WPG * s + wv) * (WAVE / 16) + rw) * MAX_OBS + (lane < G.m ? lane : 0)];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       L.P[s][k] = L.val[s] ? T[tab_basis(n, 0) + k * n + tc] : 0.f;
@@ -254,16 +300,19 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     }
   }
   // Home lanes: coefficient k of x lives in lanes 2k, 2k+1; of y and psi in 32+2k, 33+2k.
-  // Every lane computes the rows of its index k for all three applies.
+  // Every lane computes the rows of its index k for all three applies: x rows in the
+  // lower half, y rows in the upper half, heading rows in both.
   const int k_home = min((lane & 31) >> 1, NC - 1);
   const bool upper = lane >= 32;
-  // x/y step operators in FP64 (rows read from LDS when applied), heading step
-  // operator in FP32 registers
+  // x/y step operators of the lane's axis and row in FP64 registers (loaded once),
+  // heading operator row in FP32
   const double* T64 = A.tables64 + sd.table64_off;
-  const double* rowMGx = apply64 + 0 * NC * NC + k_home * NC;
-  const double* rowMx = apply64 + 1 * NC * NC + k_home * NC;
-  const double* rowMGy = apply64 + 2 * NC * NC + k_home * NC;
-  const double* rowMy = apply64 + 3 * NC * NC + k_home * NC;
+  double rowMG[NC], rowM[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    rowMG[j] = T64[(upper ? T64_MGY : T64_MGX) + k_home * NC + j];
+    rowM[j] = T64[(upper ? T64_MY : T64_MX) + k_home * NC + j];
+  }
   float rMp[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) rMp[j] = T[tab_square(n, SQ_MP) + k_home * NC + j];
@@ -274,15 +323,23 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   const float by[NY] = {e[1], e[3], e[5], gl[1], 0.f, 0.f};
   const float bp[NP] = {e[6], e[7], 0.f, 0.f};
   const float* Bt = T + tab_bnd(n);
-  double c0x = 0.0, c0y = 0.0;
+  double c0 = 0.0;  // particular part of the lane's axis and row
   float c0p = 0.f;
+  if (!upper) {
 #pragma unroll
-  for (int j = 0; j < NX; ++j) c0x = fma(T64[T64_MBX + k_home * NX + j], (double)bx[j], c0x);
+    for (int j = 0; j < NX; ++j) c0 = fma(T64[T64_MBX + k_home * NX + j], (double)bx[j], c0);
+  } else {
 #pragma unroll
-  for (int j = 0; j < NY; ++j) c0y = fma(T64[T64_MBY + k_home * NY + j], (double)by[j], c0y);
+    for (int j = 0; j < NY; ++j) c0 = fma(T64[T64_MBY + k_home * NY + j], (double)by[j], c0);
+  }
 #pragma unroll
   for (int j = 0; j < NP; ++j) c0p = fmaf(Bt[BND_MBP + k_home * NP + j], bp[j], c0p);
 
+  float* sC = slots + SLOT_C;  // coefficient broadcast
+  float* sR = slots + SLOT_R;  // x/y apply inputs
+  float* sP = slots + SLOT_P;  // heading apply input
+  float* sQ = slots + SLOT_Q;  // heading apply output
+  float* sB = slots + SLOT_B;  // row boxes of the culling
   float cx[NC], cy[NC], cp[NC];
   // multipliers at their home lanes: lxy = lambda_x[k] (lower half) / lambda_y[k] (upper
   // half); lp = lambda_psi[k] (upper half)
@@ -290,29 +347,49 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   const bool cold = (A.flags & TRAJ_INIT_FROM_STATE) == 0;
   if (cold) {
     // boundary-only minimum-acceleration start, lambda = 0
-    float vx = 0.f, vy = 0.f;
+    float v0 = 0.f;
+    if (!upper) {
 #pragma unroll
-    for (int j = 0; j < NX; ++j) vx = fmaf(Bt[BND_M0BX + k_home * NX + j], bx[j], vx);
+      for (int j = 0; j < NX; ++j) v0 = fmaf(Bt[BND_M0BX + k_home * NX + j], bx[j], v0);
+    } else {
 #pragma unroll
-    for (int j = 0; j < NY; ++j) vy = fmaf(Bt[BND_M0BY + k_home * NY + j], by[j], vy);
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      cx[j] = rdlane(vx, 2 * j);
-      cy[j] = rdlane(vy, 2 * j);
-      cp[j] = 0.f;
+      for (int j = 0; j < NY; ++j) v0 = fmaf(Bt[BND_M0BY + k_home * NY + j], by[j], v0);
     }
+    put_home(v0, sC);
     lxy = 0.f;
     lp = 0.f;
   } else {
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      cx[j] = A.c[(0 * NC + j) * NG + g];
-      cy[j] = A.c[(1 * NC + j) * NG + g];
-      cp[j] = A.c[(2 * NC + j) * NG + g];
-    }
+    if ((lane & 1) == 0 && ((lane & 31) >> 1) < NC)
+      sC[(lane >> 5) * 16 + k_home] = A.c[((upper ? 1 : 0) * NC + k_home) * NG + g];
     lxy = A.lam[((upper ? 1 : 0) * NC + k_home) * NG + g];
     lp = A.lam[(2 * NC + k_home) * NG + g];
   }
+  wave_sync_lds();
+  get_vec(sC, cx);
+  get_vec(sC + 16, cy);
+  if (cold) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cp[j] = 0.f;
+  } else {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cp[j] = A.c[(2 * NC + j) * NG + g];
+  }
+
+  // heading step (eq. 20) from rp = rho P^T theta + lambda_psi at the upper home lanes
+  auto heading_step = [&](float rp) {
+    if (upper) put_home(rp, sP - 16);  // upper set -> sP[0, NC)
+    wave_sync_lds();
+    float rv[NC];
+    get_vec(sP, rv);
+    float a0 = c0p, a1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; j += 2) a0 = fmaf(rMp[j], rv[j], a0);
+#pragma unroll
+    for (int j = 1; j < NC; j += 2) a1 = fmaf(rMp[j], rv[j], a1);
+    if (upper) put_home(a0 + a1, sQ - 16);
+    wave_sync_lds();
+    get_vec(sQ, cp);
+  };
 
   float uxy;  // u~_x[k] at lanes 2k, u~_y[k] at lanes 32+2k, residuals at lanes 22..28
   float part[32];
@@ -327,14 +404,9 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     if (cold) {
       const float wE = total(reduce32(part));
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
-      const float rp = fmaf(rho, w, lp);
-      float np = c0p;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) np = fmaf(rMp[j], rdlane(rp, 32 + 2 * j), np);
-#pragma unroll
-      for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
+      heading_step(fmaf(rho, w, lp));
     }
-    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part);
+    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part, sB);
     uxy = total(reduce32(part));
 #pragma unroll
     for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
@@ -344,26 +416,29 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   for (int it = 0; it < A.iters; ++it) {
     // ---- x/y step (eq. 12 through eq. 18):
     // c_new = M (rho F^T g + lambda) + M_b b = (M rho F_ax^T F_ax) c + M (rho u~ + lambda) + M_b b
+    // Each lane applies the row k_home of its half's axis in FP64 (four independent
+    // accumulation chains), with the axis's c and r = rho u~ + lambda read back from LDS.
     {
-      const float r = fmaf(rho, uxy, lxy);
-      float rx[NC], ry[NC];
+      put_home(fmaf(rho, uxy, lxy), sR);
+      wave_sync_lds();
+      float rv[NC], cv[NC];
+      get_vec(sR + (upper ? 16 : 0), rv);
+      get_vec(sC + (upper ? 16 : 0), cv);
+      double a0 = c0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        rx[j] = rdlane(r, 2 * j);
-        ry[j] = rdlane(r, 32 + 2 * j);
+      for (int j = 0; j < NC; j += 2) {
+        a0 = fma(rowMG[j], (double)cv[j], a0);
+        a1 = fma(rowM[j], (double)rv[j], a1);
       }
-      double nx = c0x, ny = c0y;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        nx = fma(rowMGx[j], (double)cx[j], fma(rowMx[j], (double)rx[j], nx));
-        ny = fma(rowMGy[j], (double)cy[j], fma(rowMy[j], (double)ry[j], ny));
+      for (int j = 1; j < NC; j += 2) {
+        a2 = fma(rowMG[j], (double)cv[j], a2);
+        a3 = fma(rowM[j], (double)rv[j], a3);
       }
-      const float fx = (float)nx, fy = (float)ny;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        cx[j] = rdlane(fx, 2 * j);
-        cy[j] = rdlane(fy, 2 * j);
-      }
+      put_home((float)((a0 + a2) + (a1 + a3)), sC);
+      wave_sync_lds();
+      get_vec(sC, cx);
+      get_vec(sC + 16, cy);
     }
     // ---- pending heading multiplier (eq. 24 of the previous step) and heading step
     // (eq. 13 through eq. 20)
@@ -373,15 +448,10 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       const float wE = total(reduce32(part));
       lp = fmaf(rho, wE, lp);                 // upper lanes: lambda_psi += rho P^T (theta - psi)
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
-      const float rp = fmaf(rho, w, lp);
-      float np = c0p;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) np = fmaf(rMp[j], rdlane(rp, 32 + 2 * j), np);
-#pragma unroll
-      for (int j = 0; j < NC; ++j) cp[j] = rdlane(np, 32 + 2 * j);
+      heading_step(fmaf(rho, w, lp));
     }
     // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
-    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part);
+    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part, sB);
     uxy = total(reduce32(part));
     // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
     lxy = fmaf(rho, uxy, lxy);
@@ -445,8 +515,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   __shared__ float4 sobs[MAX_OBS];                  // the scene's obstacles, scaled by (1/a, 1/b)
   __shared__ float4 box[S * WPG * (WAVE / 16) * MAX_OBS];  // per slot, row of 16 samples and obstacle:
                                                           // x range, y range (scaled, inflated)
-  __shared__ double apply64[4 * NC * NC];           // MGx, Mx, MGy, My of the scene's shape
   __shared__ float ex[2 * 2 * WAVE];                // partial sums of a goal's two waves (double-buffered)
+  __shared__ float4 slots4[GPW * WPG][SLOT_FLOATS / 4];  // each wave's broadcast slots
   __shared__ int sh[2];
   __shared__ int scan[GOALS_PER_WG];
   locate(A.goal_off, A.n_scenes, GPW, sh, scan);
@@ -486,8 +556,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
   // first and last sample (the same expression the projections evaluate).
   constexpr int ROWS = WAVE / 16;
   for (int e = tid; e < S * WPG * ROWS * m; e += THREADS) {
-    const int gr = e / m, j = e - gr * m;  // gr = slot * ROWS + row
-    const int i0 = min(16 * gr, n - 1), i1 = min(16 * gr + 15, n - 1);
+    const int gr = e / m, j = e - gr * m;  // gr = (WPG slot + wave) * ROWS + row
+    const int gs = gr / ROWS, rw = gr - gs * ROWS;
+    const int first = slot_start(n, WPG, gs % WPG, gs / WPG) + 16 * rw;
+    const int i0 = min(first, n - 1), i1 = min(first + 15, n - 1);
     const float* o = A.obs + 4 * (o0 + j);
     const float px = o[0] * inv_a, py = o[1] * inv_b, vx = o[2] * inv_a, vy = o[3] * inv_b;
     const float t0 = (float)i0 * dt, t1 = (float)i1 * dt;
@@ -496,20 +568,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
     constexpr float R = 1.001f;
     box[gr * MAX_OBS + j] = make_float4(fminf(xa, xb) - R, fmaxf(xa, xb) + R, fminf(ya, yb) - R, fmaxf(ya, yb) + R);
   }
-  const double* T64 = A.tables64 + sd.table64_off;
-  for (int e = tid; e < NC * NC; e += THREADS) {
-    apply64[0 * NC * NC + e] = T64[T64_MGX + e];
-    apply64[1 * NC * NC + e] = T64[T64_MX + e];
-    apply64[2 * NC * NC + e] = T64[T64_MGY + e];
-    apply64[3 * NC * NC + e] = T64[T64_MY + e];
-  }
   const bool scene_marked = __syncthreads_or(obs_marked) != 0 || !all_finite(A.ego + 8 * scene, 8);
   if (g >= g1) return;  // only with one wave per goal (a two-wave workgroup always has its goal)
   if (scene_marked || !all_finite(A.goal + 2 * g, 2)) {  // uniform over the goal's waves
     if (writer) write_marked_goal(A, g, tid & 63, WAVE);
     return;
   }
-  solve_goal<S, WPG>(A, sd, A.tables + sd.table_off, sobs, box, apply64, ex, scene, g);
+  solve_goal<S, WPG>(A, sd, A.tables + sd.table_off, sobs, box, ex,
+                     reinterpret_cast<float*>(slots4[tid >> 6]), scene, g);
 }
 
 // Lane-layout check of the two reductions: in[R][64] -> out[64].
