@@ -42,6 +42,9 @@ extern "C" {
 #define TRAJ_WARM_FALLBACK 0x2u   /* with FROM_STATE, group kernel: the first iteration also
                                      runs from the cold start; each goal keeps whichever has
                                      the lower max(r_obs, r_acc, r_nh) after it               */
+#define TRAJ_KEEP_DONE 0x4u       /* traj_converge only: scene_done and scene_iters are kept, not
+                                     reset; scenes already done are left untouched and the
+                                     others start as the other flags say                      */
 #define TRAJ_PREC_FP32 0x0u       /* FP32 arithmetic, x/y step operators in FP64 (default)   */
 #define TRAJ_PREC_BF16X3 0x10u    /* matrix-core kernel, every contraction and apply in split
                                      BF16 (hi + lo, three products) with FP32 accumulation   */
@@ -211,8 +214,13 @@ int traj_score(void *handle, const traj_batch *batch, const traj_state *state, c
  * chunk, so finished scenes cost only the skipped launches.
  *   flags: as traj_solve_batch for the first chunk (cold, warm, warm with
  *          TRAJ_WARM_FALLBACK; precision; kernel); later chunks resume the state.
- *   state: c, lam, resid and scene_done are required (scene_done is reset first
- *          and holds 1 for converged scenes on return).
+ *          With TRAJ_KEEP_DONE the call continues an earlier one: scene_done and
+ *          scene_iters are not reset, the scenes marked done are neither solved
+ *          nor re-scored, the others start as the flags say (for example a cold
+ *          restart of the scenes a warm start left unconverged) and scene_iters
+ *          adds this call's iterations to what it held.
+ *   state: c, lam, resid and scene_done are required (scene_done is reset first,
+ *          unless TRAJ_KEEP_DONE, and holds 1 for converged scenes on return).
  *   cost, best: as traj_score (the ranking after the last chunk).
  *   scene_iters: device [n_scenes]: iterations the scene ran (a multiple of chunk,
  *          or max_iters).

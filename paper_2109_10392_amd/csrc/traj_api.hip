@@ -272,22 +272,25 @@ int traj_converge(void* handle, const traj_batch* batch, traj_state* state, cons
   if (batch->n_scenes == 0) return TRAJ_OK;
   if (state->scene_done == nullptr || scene_iters == nullptr || best == nullptr)
     return fail(TRAJ_E_INVAL, "state.scene_done, scene_iters and best are required");
+  if (state->resid == nullptr) return fail(TRAJ_E_INVAL, "state.resid is required");
+  const bool keep_done = (flags & TRAJ_KEEP_DONE) != 0;
+  flags &= ~TRAJ_KEEP_DONE;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = traj::launch_converge_reset(state->scene_done, scene_iters, batch->n_scenes, st);
-  if (e != hipSuccess) return hip_fail(e, "traj_converge");
+  if (!keep_done) {
+    hipError_t e = traj::launch_converge_reset(state->scene_done, scene_iters, batch->n_scenes, st);
+    if (e != hipSuccess) return hip_fail(e, "traj_converge");
+  }
   const uint32_t keep = TRAJ_PREC_BF16X3 | TRAJ_KERNEL_WAVE | TRAJ_KERNEL_MFMA | TRAJ_KERNEL_GROUP;
   for (int done = 0, c = 0; done < max_iters; ++c) {
     const int it = max_iters - done < chunk ? max_iters - done : chunk;
     // the first chunk starts as the caller asked; later chunks resume the state
     const uint32_t f = c == 0 ? flags : ((flags & keep) | TRAJ_INIT_FROM_STATE);
     if ((rc = solve_impl(h, batch, state, it, 0.f, f, stream, c > 0)) != TRAJ_OK) return rc;
-    // scenes converged in an earlier chunk are neither iterated nor re-scored; the
-    // scoring also applies the stopping rule to the others
-    if (state->resid == nullptr) return fail(TRAJ_E_INVAL, "state.resid is required");
+    // scenes converged in an earlier chunk (or call, with TRAJ_KEEP_DONE) are neither
+    // iterated nor re-scored; the scoring also applies the stopping rule to the others
     const traj::ConvergeCheck check = {state->resid, state->scene_done, scene_iters, it, tol};
-    if ((rc = score_impl(h, batch, state, mc, cost, best, stream, c > 0 ? state->scene_done : nullptr, &check)) !=
-        TRAJ_OK)
-      return rc;
+    const int32_t* skip = (c > 0 || keep_done) ? state->scene_done : nullptr;
+    if ((rc = score_impl(h, batch, state, mc, cost, best, stream, skip, &check)) != TRAJ_OK) return rc;
     done += it;
   }
   return TRAJ_OK;

@@ -20,6 +20,7 @@ TRAJ_OK = 0
 TRAJ_INIT_COLD = 0x0
 TRAJ_INIT_FROM_STATE = 0x1
 TRAJ_WARM_FALLBACK = 0x2
+TRAJ_KEEP_DONE = 0x4
 TRAJ_PREC_FP32 = 0x0
 TRAJ_PREC_BF16X3 = 0x10
 TRAJ_KERNEL_AUTO = 0x0
@@ -242,9 +243,10 @@ class Solver:
 
     def converge(self, batch: DeviceBatch, state: DeviceState, v_ref, cost, best, scene_iters, max_iters=300,
                  chunk=5, tol=1e-3, from_state=False, fallback=False, precision="fp32", kernel="auto", kind=0,
-                 w1=1.0, w2=1.0, y_rl=None, clear_min=0.0, stream=None):
+                 w1=1.0, w2=1.0, y_rl=None, clear_min=0.0, stream=None, keep_done=False):
         """Chunked solve until each scene's best goal meets the residual tolerance
-        (device-side bookkeeping; state.scene_done and scene_iters hold the outcome)."""
+        (device-side bookkeeping; state.scene_done and scene_iters hold the outcome).
+        keep_done: continue an earlier call (only the scenes it left unconverged run)."""
         import torch
         if kernel == "group" or (kernel == "auto" and self.get_tile()[0] == "group"):
             self.ensure_work(batch, state)
@@ -253,8 +255,9 @@ class Solver:
         b = batch.c_struct()
         s = state.c_struct()
         mc = MetaC(int(kind), _ptr(v_ref), float(w1), float(w2), _ptr(y_rl), float(clear_min))
+        flags = self._flags(from_state, fallback, precision, kernel) | (TRAJ_KEEP_DONE if keep_done else 0)
         _check(lib().traj_converge(self.handle, ctypes.byref(b), ctypes.byref(s), ctypes.byref(mc), int(max_iters),
-                                   int(chunk), float(tol), self._flags(from_state, fallback, precision, kernel),
+                                   int(chunk), float(tol), flags,
                                    _ptr(cost), _ptr(best), _ptr(scene_iters), _stream(stream)))
 
     def solve(self, batch: DeviceBatch, state: DeviceState, iters: int, tol: float = 0.0,

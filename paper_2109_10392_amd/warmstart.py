@@ -14,9 +14,11 @@ Evaluation (the stopping rule of traj_converge: the best goal of a scene at
 max(r_obs, r_acc, r_nh) <= 1e-3, checked every 5 iterations, at most 300):
   cold: FP32 solver from the cold start;
   warm: features -> network -> (c, lambda), then the split-BF16 solver with the
-        cold start as fallback (per goal, after one iteration, whichever start
-        has the lower residual). The network, the features and the extra
-        fallback iteration are all inside the warm timing.
+        cold start as fallback twice: per goal, after one iteration, whichever
+        start has the lower residual; per scene, a scene not converged after
+        RESTART_AT iterations starts again from the cold start for the rest of
+        the budget. The network, the features and the extra fallback iteration
+        are all inside the warm timing.
 """
 from __future__ import annotations
 
@@ -29,6 +31,11 @@ from . import scenes as S
 from . import traj as T
 
 DIMS = (64, 256, 3, 16896)
+# Second fallback: the scenes a warm start has not brought to the tolerance after
+# this many iterations start again from the cold start for the rest of the budget
+# (a warm start that converges does so in about 55 iterations; one that has not by
+# 30 is more often stalled than slow).
+RESTART_AT = 30
 GOALS = 256  # template goals per scene (4 lanes x 64 slots)
 ROW = 6 * T.N_COEF * GOALS
 
@@ -163,7 +170,11 @@ class Problem:
         self.solver.converge(db, st, v_ref, cost, best, its, max_iters=max_iters, chunk=5, tol=tol,
                              precision=precision)
 
-    def solve_warm(self, bufs, net, mean, std, max_iters=300, tol=1e-3, precision="bf16x3", scratch=None):
+    def solve_warm(self, bufs, net, mean, std, max_iters=300, tol=1e-3, precision="bf16x3", scratch=None,
+                   restart_at=RESTART_AT):
+        """Network start with the cold start as fallback; with restart_at, the scenes
+        still unconverged after restart_at iterations start again from the cold
+        start for the rest of the max_iters budget."""
         import torch
         db, st, v_ref, cost, best, its = bufs
         x = features(db)
@@ -173,8 +184,12 @@ class Problem:
         acts, y = scratch
         net.forward(x, acts, y)
         rows_state(db, st, y, mean, std)
-        self.solver.converge(db, st, v_ref, cost, best, its, max_iters=max_iters, chunk=5, tol=tol,
+        first = max_iters if restart_at is None else min(restart_at, max_iters)
+        self.solver.converge(db, st, v_ref, cost, best, its, max_iters=first, chunk=5, tol=tol,
                              from_state=True, fallback=True, precision=precision)
+        if first < max_iters:
+            self.solver.converge(db, st, v_ref, cost, best, its, max_iters=max_iters - first, chunk=5, tol=tol,
+                                 precision=precision, keep_done=True)
 
 
 def make_dataset(prob, seeds, chunk=4096, max_iters=300, tol=1e-3, log=print, converged_only=False):
@@ -249,17 +264,20 @@ def fit(prob, seeds, epochs=30, batch=256, lr=2e-3, seed=0, log=print):
     return net, mean, std, info
 
 
-def evaluate(prob, net, mean, std, seeds, max_iters=300, tol=1e-3, warm_precision="bf16x3"):
+def evaluate(prob, net, mean, std, seeds, max_iters=300, tol=1e-3, warm_precision="bf16x3", restart_at=RESTART_AT,
+             modes=("cold", "warm_fp32", "warm"), common=True):
     """Cold FP32, warm FP32 and warm + mixed precision on the template scenes
-    `seeds`: iterations and ms per scene to the tolerance (capped at max_iters)."""
+    `seeds`: iterations and ms per scene to the tolerance (capped at max_iters),
+    the share of scenes that meet it, and (common) the same timings repeated on
+    only the scenes that both the cold FP32 and the warm + mixed forms bring to
+    the tolerance."""
     import torch
-    batch = template_batch(seeds)
-    out = {}
-    for mode in ("cold", "warm_fp32", "warm"):
+
+    def timed(mode, batch):
         prec = warm_precision if mode == "warm" else "fp32"
         bufs = prob.device(batch)
         run = (lambda: prob.solve_cold(bufs, max_iters, tol)) if mode == "cold" else \
-            (lambda: prob.solve_warm(bufs, net, mean, std, max_iters, tol, prec))
+            (lambda: prob.solve_warm(bufs, net, mean, std, max_iters, tol, prec, restart_at=restart_at))
         run()  # warm-up (also sizes the solver's scratch)
         torch.cuda.synchronize()
         bufs = prob.device(batch)
@@ -269,12 +287,34 @@ def evaluate(prob, net, mean, std, seeds, max_iters=300, tol=1e-3, warm_precisio
         b.record()
         torch.cuda.synchronize()
         its = bufs[5].cpu().numpy()
-        done = bufs[1].scene_done.cpu().numpy()[:batch.n_scenes]
-        out[mode] = {"ms_per_scene": a.elapsed_time(b) / batch.n_scenes, "iters_mean": float(its.mean()),
-                     "iters_median": float(np.median(its)), "converged": float(done.mean()),
-                     "iters_mean_converged": float(its[done != 0].mean()) if done.any() else None,
-                     "precision": prec if mode != "cold" else "fp32", "scenes": batch.n_scenes}
-    out["iters_ratio"] = out["warm"]["iters_mean"] / out["cold"]["iters_mean"]
-    out["iters_ratio_fp32"] = out["warm_fp32"]["iters_mean"] / out["cold"]["iters_mean"]
-    out["ms_ratio"] = out["warm"]["ms_per_scene"] / out["cold"]["ms_per_scene"]
+        done = bufs[1].scene_done.cpu().numpy()[:batch.n_scenes] != 0
+        return {"ms_per_scene": a.elapsed_time(b) / batch.n_scenes, "iters_mean": float(its.mean()),
+                "iters_median": float(np.median(its)), "converged": float(done.mean()),
+                "iters_mean_converged": float(its[done].mean()) if done.any() else None,
+                "precision": prec, "scenes": batch.n_scenes}, done, its
+
+    batch = template_batch(seeds)
+    out, done = {}, {}
+    for mode in modes:
+        out[mode], done[mode], _ = timed(mode, batch)
+    if restart_at is not None:
+        out["restart_at"] = restart_at
+    if "warm" in out and "cold" in out:
+        out["iters_ratio"] = out["warm"]["iters_mean"] / out["cold"]["iters_mean"]
+        out["ms_ratio"] = out["warm"]["ms_per_scene"] / out["cold"]["ms_per_scene"]
+    if "warm_fp32" in out and "cold" in out:
+        out["iters_ratio_fp32"] = out["warm_fp32"]["iters_mean"] / out["cold"]["iters_mean"]
+    if common and "warm" in done and "cold" in done:
+        both = done["cold"] & done["warm"]
+        sub = [seeds[i] for i in np.flatnonzero(both)]
+        if sub:
+            sb = template_batch(sub)
+            c, _, ci = timed("cold", sb)
+            w, _, wi = timed("warm", sb)
+            out["common"] = {"scenes": len(sub), "cold_ms_per_scene": c["ms_per_scene"],
+                             "warm_ms_per_scene": w["ms_per_scene"], "cold_iters_mean": c["iters_mean"],
+                             "warm_iters_mean": w["iters_mean"], "ms_ratio": w["ms_per_scene"] / c["ms_per_scene"],
+                             "iters_ratio": w["iters_mean"] / c["iters_mean"]}
+        out["converged_only_cold"] = int(np.count_nonzero(done["cold"] & ~done["warm"]))
+        out["converged_only_warm"] = int(np.count_nonzero(done["warm"] & ~done["cold"]))
     return out
