@@ -8,8 +8,9 @@ the timed region: it depends only on (T, m), not on the batch.
 Prints ONE JSON line. `value` is goal-trajectories x iterations per second on
 this GPU with inputs resident in HBM. `roofline` is for the dominant kernel
 (the fused AM kernel), from its average duration measured with HIP events on
-the stream it is launched on; `cpu_baseline` is the FP64 oracle on one core
-over a bounded sample of the same workload.
+the stream it is launched on; `cpu_baseline` is the FP64 oracle on the host's
+cores (all of them, one process per core, and one core alone) over a bounded
+sample of the same workload, with the CPU model and core count.
 """
 from __future__ import annotations
 
@@ -24,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N_COEF = 11
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (AMD datasheet; needs packed FP32 instructions)
+PEAK_FP32_UNPACKED_TFLOPS = 78.65  # the same without packed FP32, which this library is built without
 
 # HBM bytes per launch of the dominant kernel of each workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE, scaled by the same counters over a plain 256 MiB copy
@@ -72,20 +74,60 @@ def algorithmic_flops_per_goal_iter(n, m, N=N_COEF):
     return 28 * N * n + 16 * N * N + 30 * n + 8 * m * n
 
 
-def cpu_baseline(scene, iters, n_goals_sample):
+def _oracle_chunk(args):
+    """One worker of the CPU baseline: the FP64 oracle on goals [lo, hi) of the
+    dense scene of `seed`, one BLAS thread; returns the seconds of the solve."""
+    seed, lo, hi, iters = args
     from threadpoolctl import threadpool_limits
 
     from oracle import traj_oracle as O
     from paper_2109_10392_amd import scenes as S
+    sc = S.workload_dense(seed).scenes[0]
     with threadpool_limits(1):
-        prob = O.Problem(scene.n_time, scene.t_f, scene.obs.shape[0], S.DEFAULT_PARAMS)
+        prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], S.DEFAULT_PARAMS)
         t0 = time.perf_counter()
-        O.solve(prob, scene.ego, scene.obs, scene.goals[:n_goals_sample], iters)
-        dt = time.perf_counter() - t0
-    return {"value": n_goals_sample * iters / dt, "unit": "goal-trajectories*iters/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_goals_sample} of the 1024 goals of the same scene, {iters} iterations, FP64 NumPy, "
-                      f"1 BLAS thread, {dt:.1f} s on {platform.processor() or platform.machine()}"}
+        O.solve(prob, sc.ego, sc.obs, sc.goals[lo:hi], iters)
+        return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(seed, iters, one_core_goals, max_workers=16):
+    """The FP64 oracle (explicit F, NumPy/SciPy) on the host: one core on
+    `one_core_goals` goals of the dense scene, then every goal of the scene split
+    over one process per usable core (at most max_workers), one BLAS thread each.
+    Runs before the GPU is initialised (the worker processes are started fresh)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(cores, max_workers))
+    n_goals = 1024
+    dt1 = _oracle_chunk((seed, 0, one_core_goals, iters))
+    chunks = [(seed, n_goals * w // workers, n_goals * (w + 1) // workers, iters) for w in range(workers)]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_chunk, [(seed, 0, 1, 1)] * workers))  # start every worker and import first
+        t0 = time.perf_counter()
+        list(ex.map(_oracle_chunk, chunks))
+        dtn = time.perf_counter() - t0
+    model = cpu_model()
+    return {"value": n_goals * iters / dtn, "unit": "goal-trajectories*iters/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {n_goals} goals of the dense scene (seed {seed}), {iters} iterations, FP64 NumPy/SciPy "
+                      f"oracle, {workers} processes x 1 BLAS thread, {dtn:.1f} s wall on {model} "
+                      f"({cores} usable cores, {os.cpu_count()} logical CPUs)",
+            "cpu_model": model, "host_cores": cores,
+            "single_core": {"value": one_core_goals * iters / dt1, "cores": 1,
+                            "sample": f"{one_core_goals} of the 1024 goals, {iters} iterations, 1 BLAS thread, "
+                                      f"{dt1:.1f} s"}}
 
 
 def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent, one_launch_ms,
@@ -166,7 +208,7 @@ def run_warmstart(args):
     prob = W.Problem()
     train_seeds = range(1000, 1000 + args.train_scenes)
     net, mean, std, info = W.fit(prob, train_seeds, epochs=args.epochs, lr=2e-3, log=None)
-    res = W.evaluate(prob, net, mean, std, list(range(args.test_scenes)))
+    res = W.evaluate(prob, net, mean, std, list(range(args.test_scenes)), restart_at=args.restart_at or None)
     return {
         "metric": "ms/scene to residual 1e-3 (warm+mixed vs cold FP32)",
         "value": res["warm"]["ms_per_scene"],
@@ -187,7 +229,36 @@ def run_warmstart(args):
                    "train_scenes": args.train_scenes, "test_scenes": args.test_scenes, "epochs": args.epochs},
         "cold_fp32": res["cold"], "warm_fp32": res["warm_fp32"], "warm_mixed": res["warm"],
         "iters_ratio": res["iters_ratio"], "ms_ratio": res["ms_ratio"], "training": info,
+        "converged_only_cold": res.get("converged_only_cold"), "converged_only_warm": res.get("converged_only_warm"),
+        "common": res.get("common"), "restart_at": args.restart_at,
     }
+
+
+def warm_leg(train_scenes, test_scenes, epochs, restart_at):
+    """The metric's second half at reduced size: a network trained on the solved
+    template scenes `1000 .. 1000 + train_scenes`, then cold FP32 and warm + mixed
+    precision (split-BF16 solver, cold fallback) on `test_scenes` held-out scenes to
+    the stopping rule (best goal at max(r_obs, r_acc, r_nh) <= 1e-3, at most 300
+    iterations): ms per scene, converged share, and both timed again on only the
+    scenes both forms bring to 1e-3."""
+    from paper_2109_10392_amd import warmstart as W
+    prob = W.Problem()
+    net, mean, std, info = W.fit(prob, range(1000, 1000 + train_scenes), epochs=epochs, lr=2e-3, log=None)
+    res = W.evaluate(prob, net, mean, std, list(range(test_scenes)), restart_at=restart_at,
+                     modes=("cold", "warm"))
+    out = {"metric": "ms/scene to residual 1e-3 (warm+mixed vs cold FP32)", "unit": "ms/scene",
+           "higher_is_better": False,
+           "sample": f"template scenes (4 lanes x 64 goal slots, 10 obstacles, T=100 over 10 s); network trained "
+                     f"on the converged scenes among {train_scenes} solved ones ({epochs} epochs), "
+                     f"{test_scenes} held-out scenes; warm: split-BF16 solver, cold start as fallback per goal"
+                     + (f", unconverged scenes restarted cold after {restart_at} iterations" if restart_at else ""),
+           "cold_fp32": res["cold"], "warm_mixed": res["warm"], "ms_ratio": res["ms_ratio"],
+           "iters_ratio": res["iters_ratio"], "converged_cold": res["cold"]["converged"],
+           "converged_warm": res["warm"]["converged"], "converged_only_cold": res.get("converged_only_cold"),
+           "converged_only_warm": res.get("converged_only_warm"), "common": res.get("common"),
+           "training": info}
+    prob.solver.close()
+    return out
 
 
 def run_mpc(args):
@@ -238,7 +309,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="uneven: skip the graph-replay and separate-launch comparisons (profiling)")
-    ap.add_argument("--cpu-goals", type=int, default=640, help="goals of the CPU oracle sample (about 15 s)")
+    ap.add_argument("--cpu-goals", type=int, default=320,
+                    help="goals of the one-core CPU oracle sample (about 8 s; the all-core leg solves all 1024)")
     ap.add_argument("--kernel", choices=["auto", "wave", "mfma", "group"], default="auto",
                     help="auto: the tile chosen by the autotuner for this workload (tuning.json), else wave")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
@@ -253,6 +325,13 @@ def main():
                     help="mpc: cruise (template goals, eq. 25) or high speed near the right lane (eq. 26)")
     ap.add_argument("--clear-min", type=float, default=1.0,
                     help="mpc: collision post-check of the ranking (scaled obstacle distance; 0 = off)")
+    ap.add_argument("--no-warm", action="store_true", help="dense: skip the reduced warm-start leg")
+    ap.add_argument("--warm-train", type=int, default=20000, help="dense: training scenes of the warm-start leg")
+    ap.add_argument("--warm-test", type=int, default=2048, help="dense: held-out scenes of the warm-start leg")
+    ap.add_argument("--warm-epochs", type=int, default=30, help="dense: training epochs of the warm-start leg")
+    ap.add_argument("--restart-at", type=int, default=30,
+                    help="warm start: restart the scenes still unconverged after this many iterations from the cold "
+                         "start (within the same 300-iteration budget; 0 = never)")
     ap.add_argument("--train-scenes", type=int, default=100000, help="warmstart: solved scenes to train on")
     ap.add_argument("--test-scenes", type=int, default=10000, help="warmstart: held-out scenes timed")
     ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
@@ -269,6 +348,9 @@ def main():
     if args.workload == "mpc":
         print(json.dumps(run_mpc(args)), flush=True)
         return
+
+    # the CPU oracle first, before anything initialises the GPU (its workers are new processes)
+    cpu = cpu_baseline(args.seed, args.iters, args.cpu_goals) if not args.no_cpu and args.workload == "dense" else None
 
     import torch
 
@@ -329,6 +411,10 @@ def main():
     flops = sum(algorithmic_flops_per_goal_iter(s.n_time, s.obs.shape[0]) * s.goals.shape[0]
                 for s in batch.scenes) * args.iters
     achieved = flops / solve_avg_s / 1e12
+    # the same count without the 8 m n obstacle tests, which exact culling skips for
+    # most pairs: a lower bound of the arithmetic the kernel really executes
+    flops_no_obs = sum(algorithmic_flops_per_goal_iter(s.n_time, 0) * s.goals.shape[0]
+                       for s in batch.scenes) * args.iters
     out = {
         "metric": "goal-trajectories*iters/s",
         "value": value,
@@ -340,7 +426,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        # FP32 arithmetic with the 11x11 x/y applies in FP64; the split-BF16 form's
+        # evaluations and contractions in BF16 (hi + lo) on the matrix cores
+        "dtype": "f32+f64" if args.precision == "fp32" else "bf16x3+f32+f64",
         "data": "synthetic",
         "config": ({"workload": "dense highway scene: 1 scene x 1024 goals, 50 obstacles, 6 lanes, "
                                 "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
@@ -356,14 +444,19 @@ def main():
                      "traffic": measured_traffic(args.workload, kernel, waves, args.precision),
                      "kernel": {"wave": "k_am (wave kernel)", "mfma": "k_am_mfma", "group": "k_am_group"}[kernel],
                      "kernel_ms": solve_avg_s * 1e3,
-                     "algorithmic_flop_per_launch": flops},
+                     "algorithmic_flop_per_launch": flops,
+                     "frac_without_obstacle_tests": flops_no_obs / solve_avg_s / 1e12 / PEAK_FP32_TFLOPS,
+                     "frac_of_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                     "target_frac": 0.5},
         "best_goal": int(best[0].item()),
     }
     if args.workload == "uneven" and not args.no_extras:
         out["uneven"] = uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent,
                                       total_ms / args.steps, waves)
-    if not args.no_cpu and args.workload == "dense":
-        out["cpu_baseline"] = cpu_baseline(sc, args.iters, args.cpu_goals)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if args.workload == "dense" and not args.no_warm:
+        out["warmstart"] = warm_leg(args.warm_train, args.warm_test, args.warm_epochs, args.restart_at or None)
     solver.close()
     print(json.dumps(out), flush=True)
 
