@@ -595,3 +595,33 @@ def _check_planted(ns):
             best = int(np.nanargmin(np.sum((v - float(sc.ego[2])) ** 2, axis=0)))
         h = st.hist[:, :3, best]
         assert not (np.all(np.isfinite(st.hist)) and h[-1].max() < h[0].max()), seed
+
+
+def test_multiplier_components_along_the_boundary_rows_change_no_iterate():
+    """The multipliers enter eqs. 17 and 19 only through the right-hand side of a
+    KKT system whose equality rows are A (eq. 8b): adding A^T v to lambda is
+    absorbed by the equality multiplier. Resuming the oracle from (c, lambda) and
+    from (c, lambda + A^T v) for random v gives the same coefficients after
+    several iterations, while the same-size change outside the rows of A does not.
+    This is why the parity tests compare lambda modulo the rows of A."""
+    sc = S.workload_small(3).scenes[0]
+    prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+    st = O.solve(prob, sc.ego, sc.obs, sc.goals, 20)
+    init = {k: getattr(st, k).copy() for k in ("c_x", "c_y", "c_psi", "lam_x", "lam_y", "lam_psi")}
+    rng = np.random.default_rng(0)
+    B = sc.goals.shape[0]
+    moved = dict(init)
+    other = dict(init)
+    for name, A in (("lam_x", prob.A_x), ("lam_y", prob.A_y), ("lam_psi", prob.A_psi)):
+        v = rng.normal(0, 5.0, (A.shape[0], B))
+        moved[name] = init[name] + A.T @ v
+        w = rng.normal(0, 1.0, (prob.N, B))
+        w -= A.T @ np.linalg.solve(A @ A.T, A @ w)  # outside the rows of A
+        other[name] = init[name] + w
+    a = O.solve(prob, sc.ego, sc.obs, sc.goals, 5, init=init)
+    b = O.solve(prob, sc.ego, sc.obs, sc.goals, 5, init=moved)
+    c = O.solve(prob, sc.ego, sc.obs, sc.goals, 5, init=other)
+    for name in ("c_x", "c_y", "c_psi"):
+        ref = getattr(a, name)
+        assert np.max(np.abs(getattr(b, name) - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))
+    assert max(np.max(np.abs(getattr(c, n) - getattr(a, n))) for n in ("c_x", "c_y", "c_psi")) > 1e-3
