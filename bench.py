@@ -166,6 +166,22 @@ def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, 
     graph_ms = a.elapsed_time(b) / args.steps
     graph_equal = bool(torch.equal(st.c, ref_c))
 
+    # the single tile: every shape at the tile's group size (the per-bucket sizes off)
+    groups = solver.get_shape_groups()
+    single_ms, single_equal = None, None
+    if kernel == "group" and any(groups):
+        solver.set_shape_groups(None)
+        step()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(args.steps):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        single_ms = a.elapsed_time(b) / args.steps
+        single_equal = bool(torch.equal(st.c, ref_c))
+        solver.set_shape_groups(groups)
+
     # one launch per scene: per-scene batches and states (goal-fastest layouts do
     # not allow views of one scene inside the batch state)
     parts = []
@@ -195,7 +211,10 @@ def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, 
     sep_equal = all(torch.equal(p[1].c, ref_c[:, :, off[i]:off[i + 1]]) for i, p in enumerate(parts))
     return {"one_launch_ms": one_launch_ms, "graph_replay_ms": graph_ms, "separate_launches_ms": sep_ms,
             "speedup_vs_separate": sep_ms / graph_ms, "graph_equals_eager": graph_equal,
-            "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent, waves]}
+            "separate_equals_batched": bool(sep_equal), "tile": [kernel, group, persistent, waves],
+            "single_tile_step_ms": single_ms,
+            "gain_over_single_tile": None if single_ms is None else single_ms / one_launch_ms,
+            "single_tile_equals": single_equal}
 
 
 def run_warmstart(args):
@@ -377,6 +396,13 @@ def main():
     if args.precision == "bf16x3" and kernel == "wave":
         kernel = "mfma"
     solver.set_tile(kernel, group, persistent, waves)
+    buckets = None
+    if args.kernel == "auto" and kernel == "group" and args.group is None:
+        # the group kernel's per-(T, m) bucket group sizes, where the autotuner stored any
+        from paper_2109_10392_amd import autotune
+        buckets = autotune.lookup_buckets(args.workload, args.precision)
+        if buckets:
+            solver.set_shape_groups(autotune.shape_groups(batch.shapes(), buckets))
     db = T.DeviceBatch.from_batch(batch)
     st = T.DeviceState.empty(B)
     v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
@@ -438,7 +464,7 @@ def main():
                                 "T in {50,100,150}, 100 AM iterations (cold start) + scoring",
                     "goals": B, "scenes": batch.n_scenes})
         | {"iters": args.iters, "seed": args.seed, "kernel": kernel, "group": group, "persistent": persistent,
-           "waves": waves},
+           "waves": waves} | ({"bucket_groups": buckets} if buckets else {}),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(args.workload, kernel, waves, args.precision),

@@ -274,13 +274,33 @@ int traj_get_tile(void *handle, traj_tile *tile);
 /*
  * traj_work_ints -- entries of the int32 device scratch (traj_state.work) that a
  * group-kernel solve of a batch with n_scenes scenes and n_goals goals needs with
- * the handle's current group size: 4 + 2 (ceil(n_goals / group) + n_scenes) +
- * n_goals + n_scenes (claim counter, the cost-sorted list of goal groups, the goal
- * order of every scene, the goals of each scene that are solved). The wave and
- * MFMA kernels do not use the scratch. Host-only.
+ * the handle's current group sizes: 4 + 2 (ceil(n_goals / group) + n_scenes) +
+ * n_goals + n_scenes with group the smallest goals-per-group of any shape (the
+ * tile's where a shape sets none; claim counter, the cost-sorted list of goal
+ * groups, the goal order of every scene, the goals of each scene that are
+ * solved). The wave and MFMA kernels do not use the scratch. Host-only.
  * Errors: TRAJ_E_INVAL (NULL handle or out, negative sizes).
  */
 int traj_work_ints(void *handle, int n_scenes, int n_goals, int64_t *out);
+
+/*
+ * traj_set_shape_groups / traj_get_shape_groups -- goals per group of the group
+ * kernel (TRAJ_KERNEL_GROUP) for the scenes of each shape, as a per-(T, m)
+ * autotuner chooses them; the other kernels ignore it. The operation is that of
+ * traj_solve_batch (Algorithm 1 per goal, Sec. III-D): the sizes change only how
+ * goals are packed onto wavefronts, never a result.
+ *   groups: host, one int32 per shape of the handle (setup order): 0 = the tile's
+ *           group size (the initial setting), 1..16 = that many goals per group;
+ *           NULL sets every shape to 0. get writes the same layout.
+ * set copies the shape table to the device with a synchronous copy: no solve on
+ * this handle may be running (synchronise its streams first). Raising the
+ * smallest group size never invalidates a work buffer sized before; lowering it
+ * can (traj_work_ints).
+ * Errors: TRAJ_E_INVAL (NULL handle or out, a size outside 0..16; nothing is
+ * changed), TRAJ_E_HIP.
+ */
+int traj_set_shape_groups(void *handle, const int32_t *groups);
+int traj_get_shape_groups(void *handle, int32_t *groups);
 
 /* traj_destroy -- free the handle's device memory. NULL is a no-op. */
 int traj_destroy(void *handle);

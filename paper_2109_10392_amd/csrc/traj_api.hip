@@ -104,6 +104,15 @@ struct Handle {
 
 bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
 
+// Smallest goals-per-group of the group kernel over the handle's shapes (a shape
+// without its own size takes the tile's): sizes the group kernel's work list.
+int min_group(const Handle* h) {
+  int g = h->tile.group;
+  for (const ShapeDesc& s : h->shapes)
+    if (s.group >= 1 && s.group < g) g = s.group;
+  return g;
+}
+
 traj::SolverConst consts(const traj_params& p) {
   traj::SolverConst k;
   k.rho = p.rho;
@@ -163,7 +172,7 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
       return fail(TRAJ_E_INVAL, "shape %d invalid (n_time in [%d, %d], t_f > 0, n_obs in [0, %d])", i, traj::NC,
                   traj::MAX_TIME, traj::MAX_OBS);
     }
-    ShapeDesc d;
+    ShapeDesc d = {};
     d.n = s.n_time;
     d.m = s.n_obs;
     d.t_f = s.t_f;
@@ -328,13 +337,13 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
   if (state->c == nullptr || state->lam == nullptr) return fail(TRAJ_E_INVAL, "state.c / state.lam is NULL");
   int32_t* work = state->work;
   if (kernel == TRAJ_KERNEL_GROUP) {
-    const int64_t need = traj::group_work_ints(batch->n_scenes, batch->n_goals, h->tile.group);
+    const int64_t need = traj::group_work_ints(batch->n_scenes, batch->n_goals, min_group(h));
     if (static_work != nullptr) {
       if (need > (int64_t)TRAJ_NOALLOC_WORK_INTS)
         return fail(TRAJ_E_INVAL,
                     "traj_solve_batch_noalloc: the group kernel's work list for %d scenes and %d goals (group "
                     "size %d) needs %lld int32, more than the library scratch of %d",
-                    batch->n_scenes, batch->n_goals, h->tile.group, (long long)need, TRAJ_NOALLOC_WORK_INTS);
+                    batch->n_scenes, batch->n_goals, min_group(h), (long long)need, TRAJ_NOALLOC_WORK_INTS);
       work = static_work;
     } else if (state->work == nullptr || state->work_ints < need) {
       return fail(TRAJ_E_INVAL, "the group kernel needs state.work with %lld int32 (got %lld)", (long long)need,
@@ -366,7 +375,7 @@ int solve_impl(Handle* h, const traj_batch* batch, traj_state* state, int iters,
   const int mode = (flags & TRAJ_PREC_BF16X3) ? traj::TRAJ_MODE_BF16X3 : traj::TRAJ_MODE_FP32;
   hipError_t e;
   if (kernel == TRAJ_KERNEL_GROUP) {
-    e = traj::launch_solve_group(a, mode, h->tile.group, h->tile.persistent != 0, h->resident_blocks[mode],
+    e = traj::launch_solve_group(a, mode, h->tile.group, min_group(h), h->tile.persistent != 0, h->resident_blocks[mode],
                                  work, reuse_order, (hipStream_t)stream);
   } else if (kernel == TRAJ_KERNEL_MFMA) {
     const size_t need = traj::mfma_smem_bytes(h->max_n, h->max_m);
@@ -496,7 +505,31 @@ int traj_work_ints(void* handle, int n_scenes, int n_goals, int64_t* out) {
   Handle* h = (Handle*)handle;
   if (h == nullptr || out == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
   if (n_scenes < 0 || n_goals < 0) return fail(TRAJ_E_INVAL, "negative batch size");
-  *out = traj::group_work_ints(n_scenes, n_goals, h->tile.group);
+  *out = traj::group_work_ints(n_scenes, n_goals, min_group(h));
+  return TRAJ_OK;
+}
+
+int traj_set_shape_groups(void* handle, const int32_t* groups) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr) return fail(TRAJ_E_INVAL, "NULL handle");
+  std::vector<ShapeDesc> next = h->shapes;
+  for (size_t i = 0; i < next.size(); ++i) {
+    const int g = groups == nullptr ? 0 : groups[i];
+    if (g < 0 || g > 16) return fail(TRAJ_E_INVAL, "shape %zu: group size %d outside 0..16", i, g);
+    next[i].group = g;
+  }
+  const hipError_t e = hipMemcpy(h->d_shapes, next.data(), sizeof(ShapeDesc) * next.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "traj_set_shape_groups");
+  h->shapes = next;
+  return TRAJ_OK;
+}
+
+int traj_get_shape_groups(void* handle, int32_t* groups) {
+  g_err.clear();
+  Handle* h = (Handle*)handle;
+  if (h == nullptr || groups == nullptr) return fail(TRAJ_E_INVAL, "NULL argument");
+  for (size_t i = 0; i < h->shapes.size(); ++i) groups[i] = h->shapes[i].group;
   return TRAJ_OK;
 }
 

@@ -121,9 +121,10 @@ __device__ __forceinline__ void sincos_heading(float x, float* sn, float* cs) {
 }
 
 // atan2 of a heading direction. First octant: a = min(|x|, |y|) / max(|x|, |y|)
-// in [0, 1]; atan(a) = a p(a^2) with p a degree-9 polynomial in a^2 fitted for
-// relative error to atan(sqrt(s)) / sqrt(s) on [0, 1] (reweighted least squares
-// on Chebyshev nodes; 1.2 units in the last place at most in FP32 Horner form);
+// in [0, 1]; atan(a) = a p(a^2) with p a degree-9 polynomial in a^2, p(0) = 1,
+// fitted for relative error to atan(sqrt(s)) / sqrt(s) on [0, 1] (Lawson's
+// reweighted least squares on Chebyshev nodes, fit_atan2_poly.py in this folder
+// with its defaults; 1.24 units in the last place at most in FP32 Horner form);
 // then pi/2 - r past the diagonal, pi - r for negative x (sign bit, so -0 counts)
 // and the sign of y. Special cases as IEEE atan2: (+-0, +0) -> +-0,
 // (+-0, -0) -> +-pi, both infinite -> +-pi/4 or +-3pi/4, NaN in -> NaN. Tiny
@@ -138,15 +139,15 @@ __device__ __forceinline__ float atan2_heading(float y, float x) {
   a = (mn == mx) ? 1.f : a;   // equal magnitudes, both infinite included
   a = (mn == 0.f) ? 0.f : a;  // an axis (both zero included)
   const float s = a * a;
-  float p = -1.7538585e-03f;
-  p = fmaf(p, s, 1.0726622e-02f);
-  p = fmaf(p, s, -3.0803997e-02f);
-  p = fmaf(p, s, 5.7551499e-02f);
-  p = fmaf(p, s, -8.3772801e-02f);
-  p = fmaf(p, s, 1.0942019e-01f);
-  p = fmaf(p, s, -1.4261931e-01f);
-  p = fmaf(p, s, 1.9998266e-01f);
-  p = fmaf(p, s, -3.3333284e-01f);
+  float p = -1.79358129e-03f;
+  p = fmaf(p, s, 1.09144244e-02f);
+  p = fmaf(p, s, -3.11775077e-02f);
+  p = fmaf(p, s, 5.79572544e-02f);
+  p = fmaf(p, s, -8.40343013e-02f);
+  p = fmaf(p, s, 1.09521791e-01f);
+  p = fmaf(p, s, -1.42642409e-01f);
+  p = fmaf(p, s, 1.99985474e-01f);
+  p = fmaf(p, s, -3.33332986e-01f);
   p = fmaf(p, s, 1.0f);
   float r = a * p;
   r = (ay > ax) ? 1.57079637f - r : r;
@@ -197,10 +198,27 @@ __device__ __forceinline__ float reduce16(const float (&v)[16]) {
 }
 
 
-// Workgroup -> (scene, first goal): scene s owns ceil(goals_s / per_item)
-// consecutive workgroups. Returns scene -1 past the last one. scan needs one
-// int per wave of the workgroup.
-__device__ void locate(const int32_t* goal_off, int n_scenes, int per_item, int* sh, int* scan) {
+// Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals workgroups
+// round robin over the device's eight XCDs). xcd_block(b, nb) renumbers them in
+// tiles of 256: within a tile, XCD x takes the 32 consecutive work items
+// [32 x, 32 x + 32), so the goal-fastest outputs of 32 neighbouring items (a
+// 128-byte line per output row when an item is one goal) are all written through
+// one L2, which writes the lines back whole instead of in 4-byte pieces. The
+// items resident on one XCD at a time still spread over the whole range, as in
+// the plain order: one contiguous range per XCD would gather neighbouring goals,
+// whose costs are alike, onto the same compute units. The last partial tile keeps
+// the plain order. A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int XCDS = 8, RUN = 32, TILE = XCDS * RUN;
+  if (b >= nb / TILE * TILE) return b;
+  const int r = b % TILE;
+  return b - r + (r % XCDS) * RUN + r / XCDS;
+}
+
+// Work item -> (scene, first goal): scene s owns ceil(goals_s / per_item)
+// consecutive items. Returns scene -1 past the last one. scan needs one int per
+// wave of the workgroup.
+__device__ void locate(const int32_t* goal_off, int n_scenes, int per_item, int* sh, int* scan, int block) {
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1), wv = tid >> 6;
   if (tid == 0) {
@@ -228,13 +246,13 @@ __device__ void locate(const int32_t* goal_off, int n_scenes, int per_item, int*
     }
     incl += pre;
     const int excl = incl - cnt;
-    const int b = (int)blockIdx.x - base;
+    const int b = block - base;
     if (cnt > 0 && b >= excl && b < incl) {
       sh[0] = s;
       sh[1] = goal_off[s] + per_item * (b - excl);
     }
     base += tot;
-    if (base > (int)blockIdx.x) break;  // uniform: every thread sees the same base
+    if (base > block) break;  // uniform: every thread sees the same base
   }
   __syncthreads();
 }

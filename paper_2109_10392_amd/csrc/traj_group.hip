@@ -60,6 +60,14 @@ __device__ __forceinline__ int group_cost(const SolveArgs& A, int scene) {
   return n_tiles(n) * (32 + m);
 }
 
+// Goals per group for the scenes of one shape: the shape's own size where set
+// (the per-bucket autotuner's choice), else the tile's.
+__device__ __forceinline__ int scene_group(const SolveArgs& A, const GroupArgs& L, int s) {
+  const int sid = A.shape_id[s];
+  const int gs = (sid >= 0 && sid < A.n_shapes) ? A.shapes[sid].group : 0;
+  return (gs >= 1 && gs <= GCOLS) ? gs : L.G;
+}
+
 __device__ __forceinline__ void scene_goals(const SolveArgs& A, int s, int& g0, int& g1) {
   g0 = min(max((int)A.goal_off[s], 0), A.n_goals);
   g1 = min(max((int)A.goal_off[s + 1], g0), A.n_goals);
@@ -75,7 +83,8 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int b = tid; b < COST_BUCKETS; b += LIST_THREADS) hist[b] = 0;
   __syncthreads();
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
-    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + L.G - 1) / L.G;
+    const int G = scene_group(A, L, s);
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + G - 1) / G;
     if (cnt > 0) atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
   }
   __syncthreads();
@@ -105,11 +114,12 @@ __global__ __launch_bounds__(LIST_THREADS) void k_list(SolveArgs A, GroupArgs L)
   for (int s = tid; s < A.n_scenes; s += LIST_THREADS) {
     int g0, g1;
     scene_goals(A, s, g0, g1);
-    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + L.G - 1) / L.G;
+    const int G = scene_group(A, L, s);
+    const int cnt = (A.skip != nullptr && A.skip[s] != 0) ? 0 : (L.nvalid[s] + G - 1) / G;
     if (cnt <= 0) continue;
     int pos = atomicAdd(&hist[min(group_cost(A, s), COST_BUCKETS - 1)], cnt);
     for (int i = 0; i < cnt && pos < L.capacity; ++i, ++pos)
-      L.items[pos] = make_int2(s, g0 + i * L.G);
+      L.items[pos] = make_int2(s, g0 + i * G);
   }
   if (tid == 0) {
     L.header[0] = 0;
@@ -711,7 +721,8 @@ __global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A,
   // every wavefront leaves once the list is exhausted: the counter only grows
   while (idx < n_items) {
     const int2 it = L.items[idx];
-    solve_group<MODE>(A, L.perm, L.G, it.x, it.y, L.nvalid[it.x], lane, sobs[wv], sth[wv], sc0[wv]);
+    solve_group<MODE>(A, L.perm, scene_group(A, L, it.x), it.x, it.y, L.nvalid[it.x], lane, sobs[wv], sth[wv],
+                      sc0[wv]);
     idx = L.persistent ? claim(L.header) : n_items;
   }
 }
@@ -737,11 +748,12 @@ hipError_t group_blocks_per_cu(int mode, int* blocks) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, WAVE * GROUP_WAVES, 0);
 }
 
-hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
+hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, int G_min, bool persistent, int resident_blocks,
                               int32_t* work, bool reuse_order, hipStream_t stream) {
   if (a.n_goals <= 0) return hipSuccess;
-  if (G < 1 || G > GCOLS || work == nullptr) return hipErrorInvalidValue;
-  const int64_t cap64 = group_capacity(a.n_scenes, a.n_goals, G);
+  if (G < 1 || G > GCOLS || G_min < 1 || G_min > G || work == nullptr) return hipErrorInvalidValue;
+  // every scene's groups hold at least G_min goals (but the last): the list fits
+  const int64_t cap64 = group_capacity(a.n_scenes, a.n_goals, G_min);
   if (cap64 > (int64_t)1 << 29) return hipErrorInvalidValue;
   GroupArgs L;
   L.header = work;

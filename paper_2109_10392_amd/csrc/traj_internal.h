@@ -71,6 +71,7 @@ struct ShapeDesc {
   float t_f;
   int table_off;  // float offset of the FP32 table
   int table64_off;
+  int group;      // goals per group of the group kernel for scenes of this shape (0: the tile's)
 };
 
 struct SolverConst {
@@ -207,7 +208,9 @@ hipError_t launch_controls(const ControlArgs& a, hipStream_t stream);
 // work: int32 workspace of group_work_ints(n_scenes, n_goals, G) entries.
 int64_t group_work_ints(int n_scenes, int n_goals, int G);
 hipError_t group_blocks_per_cu(int mode, int* blocks);
-hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, bool persistent, int resident_blocks,
+// G: the tile's goals per group, used where a shape sets none; G_min: the smallest
+// group size of any shape (sizes the work list).
+hipError_t launch_solve_group(const SolveArgs& a, int mode, int G, int G_min, bool persistent, int resident_blocks,
                               int32_t* work, bool reuse_order, hipStream_t stream);
 // Convergence bookkeeping (traj_converge): zero the per-scene flags and counters
 // (the check after each chunk runs in the argmin kernel, see ConvergeCheck).

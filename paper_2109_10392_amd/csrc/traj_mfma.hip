@@ -200,7 +200,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
   __shared__ int sh[2];
   __shared__ int scan[16];
   const int Wl = (int)blockDim.x / WAVE;  // waves launched
-  locate(A.goal_off, A.n_scenes, G, sh, scan);
+  locate(A.goal_off, A.n_scenes, G, sh, scan, xcd_block((int)blockIdx.x, (int)gridDim.x));
   const int scene = sh[0];
   if (scene < 0) return;
   if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup

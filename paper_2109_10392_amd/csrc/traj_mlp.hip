@@ -25,6 +25,7 @@ int api_fail(int code, const char* fmt, ...);
 namespace {
 
 using traj::NC;
+using traj::WAVE;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -223,13 +224,27 @@ __global__ void k_loss_total(const float* __restrict__ row_loss, int rows, float
   if (threadIdx.x == 0) loss[0] = (float)(((part[0] + part[1]) + (part[2] + part[3])) * (double)inv_total);
 }
 
-// bias gradient: column sums (FP32, fixed order) of a BF16 matrix [rows][cols]
-__global__ void k_colsum_bf16(const uint16_t* __restrict__ x, int rows, int cols, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// bias gradient: column sums (FP32, fixed order) of a BF16 matrix [rows][cols].
+// A workgroup takes 64 columns; its 16 waves sum the rows r = slice (mod 16) of
+// them (one 128-byte row segment per wave and load), and the 16 partial sums are
+// added in slice order.
+constexpr int COLSUM_SLICES = 16;
+__global__ __launch_bounds__(WAVE * COLSUM_SLICES) void k_colsum_bf16(const uint16_t* __restrict__ x, int rows,
+                                                                      int cols, float* __restrict__ out) {
+  __shared__ float part[COLSUM_SLICES][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), sl = threadIdx.x / WAVE;
+  const int c = blockIdx.x * WAVE + lane;
   float acc = 0.f;
-  for (int r = 0; r < rows; ++r) acc += bf2f(x[(size_t)r * cols + c]);
-  out[c] = acc;
+  if (c < cols)
+    for (int r = sl; r < rows; r += COLSUM_SLICES) acc += bf2f(x[(size_t)r * cols + c]);
+  part[sl][lane] = acc;
+  __syncthreads();
+  if (sl == 0 && c < cols) {
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < COLSUM_SLICES; ++i) sum += part[i][lane];
+    out[c] = sum;
+  }
 }
 
 __global__ void k_adam(float* __restrict__ p, uint16_t* __restrict__ pb, const float* __restrict__ g,
@@ -450,7 +465,8 @@ int traj_mlp_backward(const traj_mlp* net, const uint16_t* acts, const uint16_t*
     gw.C32 = net->grad + wo;
     e = gemm(true, false, gw, st);
     if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_for(fo, 256)), dim3(256), 0, st, g, batch, fo, net->grad + bo);
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_for(fo, WAVE)), dim3(WAVE * COLSUM_SLICES), 0, st, g, batch, fo,
+                       net->grad + bo);
     e = hipGetLastError();
     if (e != hipSuccess || l == 0) break;
     // g_{l-1} = bf16((g W_l^T) * (a_l > 0))   ([batch][fi], K = fo)

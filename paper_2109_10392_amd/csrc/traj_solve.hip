@@ -89,6 +89,25 @@ __device__ __forceinline__ void put_home(float v, float* slot) {
   if ((lane & 1) == 0 && k < NC) slot[(lane >> 5) * 16 + k] = v;
 }
 
+// The same in FP64: lane 2k (k < NC) writes value k of the lower set to slot[k],
+// lane 32 + 2k value k of the upper set to slot[12 + k].
+__device__ __forceinline__ void put_home64(double v, double* slot) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int k = (lane & 31) >> 1;
+  if ((lane & 1) == 0 && k < NC) slot[(lane >> 5) * 12 + k] = v;
+}
+
+__device__ __forceinline__ void get_vec64(const double* slot, double (&v)[NC]) {
+  const double2* s2 = reinterpret_cast<const double2*>(slot);
+#pragma unroll
+  for (int i = 0; i < NC / 2; ++i) {
+    const double2 d = s2[i];
+    v[2 * i] = d.x;
+    v[2 * i + 1] = d.y;
+  }
+  v[NC - 1] = s2[NC / 2].x;
+}
+
 // The NC values at slot[0, NC) into registers (every lane reads the same words).
 __device__ __forceinline__ void get_vec(const float* slot, float (&v)[NC]) {
   const float4* s4 = reinterpret_cast<const float4*>(slot);
@@ -104,15 +123,23 @@ __device__ __forceinline__ void get_vec(const float* slot, float (&v)[NC]) {
 __host__ __device__ inline int wave_span(int n, int wpg) { return (n + wpg - 1) / wpg; }
 __host__ __device__ inline int slot_start(int n, int wpg, int w, int s) { return w * wave_span(n, wpg) + WAVE * s; }
 
-// Basis rows of the lane's samples, their times, and each slot's culling boxes of
-// the lane's obstacle (one per row of 16 samples; loop-invariant, held in registers).
+// Basis rows of the lane's samples, their times, the lane's obstacle (scaled
+// state) and each slot's culling boxes of it (one per row of 16 samples);
+// loop-invariant, held in registers.
 template <int S>
 struct Lane {
   float P[S][NC], Pd[S][NC], Pdd[S][NC];
   float tm[S];
+  float4 ob;
   float4 box[S][WAVE / 16];
   bool val[S];
 };
+
+// Scaled obstacle state that no trajectory sample reaches: (x/a - 1e30)^2
+// overflows to +inf, so the test q < 1 fails.
+constexpr float UNREACHABLE = 1e30f;
+// Entries of a wave's candidate list: every obstacle plus seven padding entries.
+constexpr int CLIST = MAX_OBS + 7;
 
 __device__ __forceinline__ float dotc(const float (&r)[NC], const float (&c)[NC]) {
   float acc = 0.f;
@@ -150,11 +177,10 @@ __device__ __forceinline__ void heading_input(const Lane<S>& L, const float (&cx
 // increment of eq. 23 divided by rho, formed from per-sample residuals. Also the
 // squared residual components, and e_psi = theta - psi per slot for eq. 24.
 template <int S, int WPG>
-__device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float4* __restrict__ sobs,
-                                            const float4* __restrict__ box,
-                                            const float (&cx)[NC], const float (&cy)[NC], const float (&cp)[NC],
-                                            const float (&xd)[S], const float (&yd)[S], const float (&th)[S],
-                                            float (&ep)[S], float (&part)[32], float* bslot) {
+__device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, const float (&cx)[NC],
+                                            const float (&cy)[NC], const float (&cp)[NC], const float (&xd)[S],
+                                            const float (&yd)[S], const float (&th)[S], float (&ep)[S],
+                                            float (&part)[32], float4* clist) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = (threadIdx.x >> 6) % WPG;
 #pragma unroll
@@ -187,34 +213,35 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     const float inf = __builtin_inff();
     const float xlo = row_min(L.val[s] ? X : inf), xhi = row_max(L.val[s] ? X : -inf);
     const float ylo = row_min(L.val[s] ? Y : inf), yhi = row_max(L.val[s] ? Y : -inf);
-    // each row's box to every lane through the wave's LDS slot
-    if ((lane & 15) == 0) reinterpret_cast<float4*>(bslot)[lane >> 4] = make_float4(xlo, xhi, ylo, yhi);
-    wave_sync_lds();
+    // lane j tests obstacle j against each row's box, read from the row's first lane.
+    // The reads stay outside any lane-dependent branch (bitwise, not short-circuit,
+    // tests): a lane read while inactive would return a stale register.
     bool hit = false;
 #pragma unroll
     for (int rw = 0; rw < WAVE / 16; ++rw) {
-      const float4 rb = reinterpret_cast<const float4*>(bslot)[rw];
+      const float rxl = rdlane(xlo, 16 * rw), rxh = rdlane(xhi, 16 * rw);
+      const float ryl = rdlane(ylo, 16 * rw), ryh = rdlane(yhi, 16 * rw);
       const float4 bx = L.box[s][rw];
-      hit = hit || ((rb.y > bx.x) && (rb.x < bx.y) && (rb.w > bx.z) && (rb.z < bx.w));
+      hit = hit | ((rxh > bx.x) & (rxl < bx.y) & (ryh > bx.z) & (ryl < bx.w));
     }
-    unsigned long long cand = __ballot(hit && lane < G.m);
+    // The candidates' scaled states, compacted in index order into the wave's
+    // list and followed by seven unreachable entries, so that rounds of four read
+    // the next round's entries before testing their own without a bound check.
+    hit = hit && lane < G.m;
+    const unsigned long long cand = __ballot(hit);
+    const int cnt = __popcll(cand);
+    if (hit) clist[__builtin_amdgcn_mbcnt_hi((unsigned)(cand >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)cand, 0u))] = L.ob;
+    if (lane < 7) clist[cnt + lane] = make_float4(UNREACHABLE, UNREACHABLE, 0.f, 0.f);
+    wave_sync_lds();
     const float tm = L.tm[s];
     float Sx = 0.f, Sy = 0.f, ro = 0.f;
-    while (cand) {
-      // up to four candidates per round, their LDS reads issued together
-      int jj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        jj[u] = cand ? __builtin_ctzll(cand) : -1;
-        cand &= cand - 1;
-      }
+    auto test4 = [&](const float4 (&o)[4]) {
       float tx[4], ty[4], qq[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float4 o = sobs[jj[u] < 0 ? 0 : jj[u]];
-        tx[u] = X - fmaf(o.z, tm, o.x);
-        ty[u] = Y - fmaf(o.w, tm, o.y);
-        qq[u] = jj[u] < 0 ? 2.f : fmaf(tx[u], tx[u], ty[u] * ty[u]);
+        tx[u] = X - fmaf(o[u].z, tm, o[u].x);
+        ty[u] = Y - fmaf(o[u].w, tm, o[u].y);
+        qq[u] = fmaf(tx[u], tx[u], ty[u] * ty[u]);
       }
       if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
@@ -231,7 +258,23 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
           }
         }
       }
+    };
+    // rounds of four in two alternating register sets: each round's reads are
+    // issued before the previous round is tested (indices stay below cnt + 7)
+    float4 oa[4], ob[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) oa[u] = clist[u];
+    for (int c0 = 0; c0 < cnt; c0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ob[u] = clist[c0 + 4 + u];
+      test4(oa);
+      if (c0 + 4 >= cnt) break;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) oa[u] = clist[c0 + 8 + u];
+      test4(ob);
     }
+    // the list is rewritten by the next slot or iteration: every lane's reads first
+    wave_sync_lds();
     const float sox = G.a * Sx, soy = G.b * Sy;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -249,14 +292,15 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
 }
 
 // Per-wave LDS slots of solve_goal (floats): coefficient broadcast (x at [0, 16),
-// y at [16, 32)), apply inputs (same layout), heading step input and output, the
-// row boxes of the obstacle culling.
-constexpr int SLOT_C = 0, SLOT_R = 32, SLOT_P = 64, SLOT_Q = 80, SLOT_B = 96, SLOT_FLOATS = 112;
+// y at [16, 32)), heading step input and output; then (doubles) the x/y step's
+// operands in FP64: coefficients (x at [0, 12), y at [12, 24)) and right-hand
+// sides (same layout).
+constexpr int SLOT_C = 0, SLOT_P = 32, SLOT_Q = 48, SLOT_D = 64, SLOT_FLOATS = 160;
 
 template <int S, int WPG>
 __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float* __restrict__ T,
                            const float4* __restrict__ sobs, const float4* __restrict__ box, float* ex, float* slots,
-                           int scene, int g) {
+                           float4* clist, int scene, int g) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = (threadIdx.x >> 6) % WPG;
   int buf = 0;
@@ -282,6 +326,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   const int n = G.n;
 
   Lane<S> L;
+  L.ob = lane < G.m ? sobs[lane] : make_float4(UNREACHABLE, UNREACHABLE, 0.f, 0.f);
   const int span = wave_span(n, WPG);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -336,10 +381,10 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
   for (int j = 0; j < NP; ++j) c0p = fmaf(Bt[BND_MBP + k_home * NP + j], bp[j], c0p);
 
   float* sC = slots + SLOT_C;  // coefficient broadcast
-  float* sR = slots + SLOT_R;  // x/y apply inputs
   float* sP = slots + SLOT_P;  // heading apply input
   float* sQ = slots + SLOT_Q;  // heading apply output
-  float* sB = slots + SLOT_B;  // row boxes of the culling
+  double* sC64 = reinterpret_cast<double*>(slots + SLOT_D);  // x/y step operands in FP64
+  double* sR64 = sC64 + 24;
   float cx[NC], cy[NC], cp[NC];
   // multipliers at their home lanes: lxy = lambda_x[k] (lower half) / lambda_y[k] (upper
   // half); lp = lambda_psi[k] (upper half)
@@ -356,11 +401,13 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       for (int j = 0; j < NY; ++j) v0 = fmaf(Bt[BND_M0BY + k_home * NY + j], by[j], v0);
     }
     put_home(v0, sC);
+    put_home64((double)v0, sC64);
     lxy = 0.f;
     lp = 0.f;
   } else {
-    if ((lane & 1) == 0 && ((lane & 31) >> 1) < NC)
-      sC[(lane >> 5) * 16 + k_home] = A.c[((upper ? 1 : 0) * NC + k_home) * NG + g];
+    const float c_in = A.c[((upper ? 1 : 0) * NC + k_home) * NG + g];
+    put_home(c_in, sC);
+    put_home64((double)c_in, sC64);
     lxy = A.lam[((upper ? 1 : 0) * NC + k_home) * NG + g];
     lp = A.lam[(2 * NC + k_home) * NG + g];
   }
@@ -406,7 +453,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
       heading_step(fmaf(rho, w, lp));
     }
-    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part, sB);
+    projections<S, WPG>(G, L, cx, cy, cp, xd, yd, th, ep, part, clist);
     uxy = total(reduce32(part));
 #pragma unroll
     for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
@@ -417,25 +464,28 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     // ---- x/y step (eq. 12 through eq. 18):
     // c_new = M (rho F^T g + lambda) + M_b b = (M rho F_ax^T F_ax) c + M (rho u~ + lambda) + M_b b
     // Each lane applies the row k_home of its half's axis in FP64 (four independent
-    // accumulation chains), with the axis's c and r = rho u~ + lambda read back from LDS.
+    // accumulation chains), with the axis's c and r = rho u~ + lambda read back from LDS
+    // (written there in FP64 by their home lanes: the FP32 values, widened once).
     {
-      put_home(fmaf(rho, uxy, lxy), sR);
+      put_home64((double)fmaf(rho, uxy, lxy), sR64);
       wave_sync_lds();
-      float rv[NC], cv[NC];
-      get_vec(sR + (upper ? 16 : 0), rv);
-      get_vec(sC + (upper ? 16 : 0), cv);
+      double rv[NC], cv[NC];
+      get_vec64(sR64 + (upper ? 12 : 0), rv);
+      get_vec64(sC64 + (upper ? 12 : 0), cv);
       double a0 = c0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
       for (int j = 0; j < NC; j += 2) {
-        a0 = fma(rowMG[j], (double)cv[j], a0);
-        a1 = fma(rowM[j], (double)rv[j], a1);
+        a0 = fma(rowMG[j], cv[j], a0);
+        a1 = fma(rowM[j], rv[j], a1);
       }
 #pragma unroll
       for (int j = 1; j < NC; j += 2) {
-        a2 = fma(rowMG[j], (double)cv[j], a2);
-        a3 = fma(rowM[j], (double)rv[j], a3);
+        a2 = fma(rowMG[j], cv[j], a2);
+        a3 = fma(rowM[j], rv[j], a3);
       }
-      put_home((float)((a0 + a2) + (a1 + a3)), sC);
+      const float cn = (float)((a0 + a2) + (a1 + a3));
+      put_home(cn, sC);
+      put_home64((double)cn, sC64);
       wave_sync_lds();
       get_vec(sC, cx);
       get_vec(sC + 16, cy);
@@ -451,7 +501,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
       heading_step(fmaf(rho, w, lp));
     }
     // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
-    projections<S, WPG>(G, L, sobs, box, cx, cy, cp, xd, yd, th, ep, part, sB);
+    projections<S, WPG>(G, L, cx, cy, cp, xd, yd, th, ep, part, clist);
     uxy = total(reduce32(part));
     // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
     lxy = fmaf(rho, uxy, lxy);
@@ -517,9 +567,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
                                                           // x range, y range (scaled, inflated)
   __shared__ float ex[2 * 2 * WAVE];                // partial sums of a goal's two waves (double-buffered)
   __shared__ float4 slots4[GPW * WPG][SLOT_FLOATS / 4];  // each wave's broadcast slots
+  __shared__ float4 clists[GPW * WPG][CLIST];           // each wave's obstacle candidates
   __shared__ int sh[2];
   __shared__ int scan[GOALS_PER_WG];
-  locate(A.goal_off, A.n_scenes, GPW, sh, scan);
+  locate(A.goal_off, A.n_scenes, GPW, sh, scan, xcd_block((int)blockIdx.x, (int)gridDim.x));
   const int scene = sh[0];
   if (scene < 0) return;
   if (A.skip != nullptr && A.skip[scene] != 0) return;  // uniform: one scene per workgroup
@@ -575,7 +626,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
     return;
   }
   solve_goal<S, WPG>(A, sd, A.tables + sd.table_off, sobs, box, ex,
-                     reinterpret_cast<float*>(slots4[tid >> 6]), scene, g);
+                     reinterpret_cast<float*>(slots4[tid >> 6]), clists[tid >> 6], scene, g);
 }
 
 // Lane-layout check of the two reductions: in[R][64] -> out[64].

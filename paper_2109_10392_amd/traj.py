@@ -81,7 +81,8 @@ MLP_EXPORTS = ("traj_mlp_param_count", "traj_mlp_sync_bf16", "traj_features", "t
 
 EXPORTS = ("traj_setup", "traj_solve_batch", "traj_solve_batch_noalloc", "traj_score", "traj_destroy", "traj_last_error",
            "traj_debug_operators", "traj_debug_table_size", "traj_debug_reduce", "traj_set_tile", "traj_get_tile",
-           "traj_work_ints", "traj_converge", "traj_debug_atan2", "traj_controls")
+           "traj_work_ints", "traj_converge", "traj_debug_atan2", "traj_controls", "traj_set_shape_groups",
+           "traj_get_shape_groups")
 
 _lib = None
 
@@ -110,6 +111,8 @@ def lib():
     L.traj_set_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_get_tile.argtypes = [vp, ctypes.POINTER(TileC)]
     L.traj_work_ints.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.traj_set_shape_groups.argtypes = [vp, vp]
+    L.traj_get_shape_groups.argtypes = [vp, vp]
     L.traj_converge.argtypes = [vp, ctypes.POINTER(BatchC), ctypes.POINTER(StateC), ctypes.POINTER(MetaC), i32, i32,
                                 f32, ctypes.c_uint32, vp, vp, vp, vp]
     P = ctypes.POINTER
@@ -285,6 +288,22 @@ class Solver:
     def set_tile(self, kernel: str, group: int = 16, persistent: bool = True, waves: int = 1):
         t = TileC(_KERNELS[kernel], int(group), 1 if persistent else 0, int(waves))
         _check(lib().traj_set_tile(self.handle, ctypes.byref(t)))
+
+    def set_shape_groups(self, groups=None):
+        """Goals per group of the group kernel per shape (0 = the tile's); None clears."""
+        if groups is None:
+            _check(lib().traj_set_shape_groups(self.handle, None))
+            return
+        n = len(self.shapes)
+        if len(groups) != n:
+            raise ValueError(f"need {n} group sizes, got {len(groups)}")
+        arr = (ctypes.c_int32 * n)(*[int(g) for g in groups])
+        _check(lib().traj_set_shape_groups(self.handle, arr))
+
+    def get_shape_groups(self):
+        arr = (ctypes.c_int32 * len(self.shapes))()
+        _check(lib().traj_get_shape_groups(self.handle, arr))
+        return list(arr)
 
     def get_tile(self):
         """(kernel, group, persistent, waves) of the handle's tile."""

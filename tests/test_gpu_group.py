@@ -77,6 +77,40 @@ def test_group_size_and_schedule_do_not_change_results(T):
             assert np.array_equal(out[k], ref[k]), (group, persistent, k)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_per_shape_group_sizes_do_not_change_results(T, precision):
+    """Goals per group set per shape (traj_set_shape_groups): same results bitwise as
+    one group size for all, a work list sized by the smallest size, and the
+    setting read back; sizes outside 0..16 are refused without changing it."""
+    import torch
+    batch = S.Batch([S.make_scene(21, 37, 12, n_lanes=6), S.make_scene(22, 5, 3, n_lanes=4),
+                     S.make_scene(23, 20, 40, n_lanes=6, n_time=150, t_f=15.0),
+                     S.make_scene(24, 3, 0, n_lanes=4, n_time=50, t_f=5.0),
+                     S.make_scene(25, 29, 12, n_lanes=6)])
+    ref = gpu_solve(T, batch, 30, kernel="group", group=16, persistent=True, precision=precision)
+    solver = T.Solver(PARAMS, batch.shapes())
+    solver.set_tile("group", 16, True)
+    n_shapes = len(batch.shapes())
+    for groups in ([3] * n_shapes, [(5 * i) % 17 for i in range(n_shapes)], [16 - i for i in range(n_shapes)]):
+        solver.set_shape_groups(groups)
+        assert solver.get_shape_groups() == groups
+        g_min = min([g if g > 0 else 16 for g in groups])
+        need = solver.work_ints(batch.n_scenes, batch.n_goals)
+        assert need == 4 + 2 * ((batch.n_goals + g_min - 1) // g_min + batch.n_scenes) + batch.n_goals + batch.n_scenes
+        db = T.DeviceBatch.from_batch(batch)
+        st = T.DeviceState.empty(batch.n_goals)
+        solver.solve(db, st, 30, precision=precision, kernel="group")
+        torch.cuda.synchronize()
+        for k, v in (("c", st.c), ("lam", st.lam), ("resid", st.resid), ("iters", st.iters)):
+            assert np.array_equal(v.cpu().numpy(), ref[k]), (groups, k)
+    with pytest.raises(RuntimeError):
+        solver.set_shape_groups([17] * n_shapes)
+    assert solver.get_shape_groups() == groups
+    solver.set_shape_groups(None)
+    assert solver.get_shape_groups() == [0] * n_shapes
+    solver.close()
+
+
 def test_group_resume_equals_continuous_bitwise(T):
     batch = S.workload_small(5)
     full = gpu_solve(T, batch, 100, kernel="group")
