@@ -35,13 +35,13 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.65  # the same without packed FP32, which this li
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "2bd5d67b0ee785d4c0d96fb0ec0d2f3d03575cc6d4ed18850e6f4129c436b09e",
-              "bytes_per_launch": int((279.5 * 2.0 + 2272.0) * 1024),
+              "sha256": "10dcc7f676c08d526918c802b23f52bfee0f924b0dbb8327b32116ae2ef30499",
+              "bytes_per_launch": int((244.5 * 2.0 + 284.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "560aac43abd4c468e57ba1d6f7b0a395a6832982fe42592093a29d718ee5b375",
-               "bytes_per_launch": int((84134.3 * 2.0 + 277690.0) * 1024),
+               "sha256": "d12d6a33f22df64276589864c7dc72a4c0c50bd08336d2ce9f26f166e26a8532",
+               "bytes_per_launch": int((83161.9 * 2.0 + 278148.0) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 

@@ -77,9 +77,13 @@ def time_solve(solver, db, st, iters, precision, reps):
 
 
 def tune_buckets(solver, db, st, iters, shapes, goals_per_shape, precision="fp32", options=(8, 12), reps=5,
-                 margin=0.01, log=print):
+                 margin=0.02, log=print):
     """Coordinate descent over per-bucket group sizes of the group kernel on the
-    whole batch. Returns (buckets {bucket: group}, ms with them, ms of the single tile)."""
+    whole batch. A size is kept when the solve gets faster than the best so far by
+    more than `margin`; at the end the kept table and the single tile are timed
+    again, alternately, and the table survives only if it still wins by `margin`.
+    Returns (buckets {bucket: group}, ms with them, ms of the single tile,
+    sweep {bucket: {group: ms}})."""
     keys = {}
     for i, sh in enumerate(shapes):
         keys.setdefault(bucket_of(sh), []).append(i)
@@ -93,8 +97,10 @@ def tune_buckets(solver, db, st, iters, shapes, goals_per_shape, precision="fp32
     solver.set_shape_groups(None)
     single = time_solve(solver, db, st, iters, precision, reps)
     best = single
+    sweep = {}
     log(f"  single tile (group {tile_group}): {single:.3f} ms")
     for k in order:
+        sweep[k] = {}
         for g in options:
             if g == chosen[k]:
                 continue
@@ -102,12 +108,25 @@ def tune_buckets(solver, db, st, iters, shapes, goals_per_shape, precision="fp32
             trial[k] = g
             solver.set_shape_groups(groups_of(trial))
             ms = time_solve(solver, db, st, iters, precision, reps)
+            sweep[k][g] = ms
             log(f"  {k:14s} ({sum(goals_per_shape[i] for i in keys[k]):6d} goals) group {g:2d}: {ms:.3f} ms")
             if ms < best * (1.0 - margin):
                 best, chosen = ms, trial
+    # confirm against the single tile, alternating the two settings
+    t_b, t_1 = [], []
+    for _ in range(3):
+        solver.set_shape_groups(groups_of(chosen))
+        t_b.append(time_solve(solver, db, st, iters, precision, reps))
+        solver.set_shape_groups(None)
+        t_1.append(time_solve(solver, db, st, iters, precision, reps))
+    import numpy as np
+    with_buckets, single = float(np.median(t_b)), float(np.median(t_1))
+    if not with_buckets < single * (1.0 - margin):
+        log(f"  kept table {with_buckets:.3f} ms against the single tile {single:.3f} ms: not kept")
+        chosen = {k: tile_group for k in order}
+        with_buckets = single
     solver.set_shape_groups(groups_of(chosen))
-    with_buckets = time_solve(solver, db, st, iters, precision, reps)
-    return chosen, with_buckets, single
+    return chosen, with_buckets, single, sweep
 
 
 def tune(solver, db, st, iters, precision="fp32", candidates=None, reps=3):
@@ -147,15 +166,18 @@ def store(workload: str, precision: str, sweep, path=TUNING_PATH):
         json.dump(table, f, indent=1, sort_keys=True)
 
 
-def store_buckets(workload: str, precision: str, buckets, ms_buckets, ms_single, path=TUNING_PATH):
+def store_buckets(workload: str, precision: str, buckets, ms_buckets, ms_single, sweep=None, path=TUNING_PATH):
     """Add the per-bucket group sizes to the workload's stored tile (which must exist).
-    Only buckets that differ from the tile's group size are kept."""
+    Only buckets that differ from the tile's group size are kept; the sweep's
+    timings are stored beside them."""
     with open(path) as f:
         table = json.load(f)
     entry = table[f"{workload}/{precision}"]
     entry["buckets"] = {k: g for k, g in sorted(buckets.items()) if g != entry["group"]}
     entry["buckets_ms"] = ms_buckets
     entry["single_tile_ms"] = ms_single
+    if sweep is not None:
+        entry["bucket_sweep"] = {k: {str(g): round(ms, 3) for g, ms in v.items()} for k, v in sorted(sweep.items())}
     with open(path, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
 
@@ -193,12 +215,12 @@ def main():
         goals = [0] * len(batch.shapes())
         for sc, i in zip(batch.scenes, sid):
             goals[int(i)] += sc.goals.shape[0]
-        buckets, ms_b, ms_1 = tune_buckets(solver, db, st, args.iters, batch.shapes(), goals, args.precision)
+        buckets, ms_b, ms_1, sweep = tune_buckets(solver, db, st, args.iters, batch.shapes(), goals, args.precision)
         print(f"{args.workload}/{args.precision}: single tile {ms_1:.3f} ms, per-bucket groups {ms_b:.3f} ms "
               f"(gain x{ms_1 / ms_b:.3f}); buckets changed: "
               f"{ {k: g for k, g in buckets.items() if g != tile[1]} }", flush=True)
         if args.write:
-            store_buckets(args.workload, args.precision, buckets, ms_b, ms_1, args.out)
+            store_buckets(args.workload, args.precision, buckets, ms_b, ms_1, sweep, args.out)
             print(f"stored the bucket table in {args.out}", flush=True)
         solver.close()
         return
