@@ -65,6 +65,38 @@ __device__ __forceinline__ float wave_min(float v) {
 
 __device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
 
+// Order-preserving integer key of a float: key(a) < key(b) whenever a < b (not NaN;
+// -0 sorts below +0). Integer minima and maxima fold into single DPP instructions,
+// where the float ones need canonicalising moves.
+__device__ __forceinline__ int order_key(float x) {
+  const int b = __builtin_bit_cast(int, x);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum / maximum of an integer over each DPP row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ int row_min_i(int v) {
+  constexpr int TOP = 0x7fffffff;
+  v = min(v, dpp_i<DPP_QUAD_1032>(TOP, v));
+  v = min(v, dpp_i<DPP_QUAD_2301>(TOP, v));
+  v = min(v, dpp_i<DPP_ROW_HALF_MIRROR>(TOP, v));
+  return min(v, dpp_i<DPP_ROW_MIRROR>(TOP, v));
+}
+
+__device__ __forceinline__ int row_max_i(int v) {
+  constexpr int BOTTOM = (int)0x80000000;
+  v = max(v, dpp_i<DPP_QUAD_1032>(BOTTOM, v));
+  v = max(v, dpp_i<DPP_QUAD_2301>(BOTTOM, v));
+  v = max(v, dpp_i<DPP_ROW_HALF_MIRROR>(BOTTOM, v));
+  return max(v, dpp_i<DPP_ROW_MIRROR>(BOTTOM, v));
+}
+
+__device__ __forceinline__ int rdlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
 // Minimum over each DPP row of 16 lanes, returned in every lane of the row.
 __device__ __forceinline__ float row_min(float v) {
   v = fminf(v, dpp<DPP_QUAD_1032>(v));
@@ -157,11 +189,14 @@ __device__ __forceinline__ float atan2_heading(float y, float x) {
 }
 
 // Wave-wide sums of 32 per-lane values: on return lane l holds the sum of value l >> 1.
+// LIVE: values i and i + 16 for i >= LIVE are known to be zero in every lane (their
+// first exchange is skipped).
+template <int LIVE = 16>
 __device__ __forceinline__ float reduce32(const float (&v)[32]) {
   const int lane = threadIdx.x & (WAVE - 1);
   float s[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) s[i] = swap32_add(v[i], v[i + 16]);
+  for (int i = 0; i < 16; ++i) s[i] = i < LIVE ? swap32_add(v[i], v[i + 16]) : 0.f;
   float t[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) t[i] = swap16_add(s[i], s[i + 8]);

@@ -131,7 +131,7 @@ struct Lane {
   float P[S][NC], Pd[S][NC], Pdd[S][NC];
   float tm[S];
   float4 ob;
-  float4 box[S][WAVE / 16];
+  int4 box[S][WAVE / 16];  // order keys of the box (x low, x high, y low, y high)
   bool val[S];
 };
 
@@ -210,18 +210,21 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     // obstacles. Whole slots (64 samples, 6.4 s) would let most obstacles of the
     // lanes a trajectory passes through into the loop.
     const float X = x * G.inv_a, Y = y * G.inv_b;
-    const float inf = __builtin_inff();
-    const float xlo = row_min(L.val[s] ? X : inf), xhi = row_max(L.val[s] ? X : -inf);
-    const float ylo = row_min(L.val[s] ? Y : inf), yhi = row_max(L.val[s] ? Y : -inf);
+    // the row boxes in order keys (a strict float inequality implies the same one
+    // between the keys, so no overlapping pair is lost)
+    const int kx = order_key(X), ky = order_key(Y);
+    constexpr int TOP = 0x7fffffff, BOTTOM = (int)0x80000000;
+    const int xlo = row_min_i(L.val[s] ? kx : TOP), xhi = row_max_i(L.val[s] ? kx : BOTTOM);
+    const int ylo = row_min_i(L.val[s] ? ky : TOP), yhi = row_max_i(L.val[s] ? ky : BOTTOM);
     // lane j tests obstacle j against each row's box, read from the row's first lane.
     // The reads stay outside any lane-dependent branch (bitwise, not short-circuit,
     // tests): a lane read while inactive would return a stale register.
     bool hit = false;
 #pragma unroll
     for (int rw = 0; rw < WAVE / 16; ++rw) {
-      const float rxl = rdlane(xlo, 16 * rw), rxh = rdlane(xhi, 16 * rw);
-      const float ryl = rdlane(ylo, 16 * rw), ryh = rdlane(yhi, 16 * rw);
-      const float4 bx = L.box[s][rw];
+      const int rxl = rdlane_i(xlo, 16 * rw), rxh = rdlane_i(xhi, 16 * rw);
+      const int ryl = rdlane_i(ylo, 16 * rw), ryh = rdlane_i(yhi, 16 * rw);
+      const int4 bx = L.box[s][rw];
       hit = hit | ((rxh > bx.x) & (rxl < bx.y) & (ryh > bx.z) & (ryl < bx.w));
     }
     // The candidates' scaled states, compacted in index order into the wave's
@@ -335,8 +338,10 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     const int tc = L.val[s] ? t : 0;
     L.tm[s] = (float)t * G.dt;
 #pragma unroll
-    for (int rw = 0; rw < WAVE / 16; ++rw)
-      L.box[s][rw] = box[((WPG * s + wv) * (WAVE / 16) + rw) * MAX_OBS + (lane < G.m ? lane : 0)];
+    for (int rw = 0; rw < WAVE / 16; ++rw) {
+      const float4 b = box[((WPG * s + wv) * (WAVE / 16) + rw) * MAX_OBS + (lane < G.m ? lane : 0)];
+      L.box[s][rw] = make_int4(order_key(b.x), order_key(b.y), order_key(b.z), order_key(b.w));
+    }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       L.P[s][k] = L.val[s] ? T[tab_basis(n, 0) + k * n + tc] : 0.f;
@@ -449,12 +454,12 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     float xd[S], yd[S], th[S];
     heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
     if (cold) {
-      const float wE = total(reduce32(part));
+      const float wE = total(reduce32<NC>(part));
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
       heading_step(fmaf(rho, w, lp));
     }
     projections<S, WPG>(G, L, cx, cy, cp, xd, yd, th, ep, part, clist);
-    uxy = total(reduce32(part));
+    uxy = total(reduce32<R_PSI + 1>(part));
 #pragma unroll
     for (int s = 0; s < S; ++s) ep[s] = 0.f;  // the start has no pending heading multiplier step
   }
@@ -495,14 +500,14 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     float xd[S], yd[S], th[S];
     {
       heading_input<S>(L, cx, cy, ep, xd, yd, th, part);
-      const float wE = total(reduce32(part));
+      const float wE = total(reduce32<NC>(part));
       lp = fmaf(rho, wE, lp);                 // upper lanes: lambda_psi += rho P^T (theta - psi)
       const float w = permlane_lo_to_hi(wE);  // P^T theta at lanes 32+2k
       heading_step(fmaf(rho, w, lp));
     }
     // ---- v, (alpha, d), (alpha_a, d_a): eqs. 14-16, 21-22
     projections<S, WPG>(G, L, cx, cy, cp, xd, yd, th, ep, part, clist);
-    uxy = total(reduce32(part));
+    uxy = total(reduce32<R_PSI + 1>(part));
     // ---- multipliers of the x/y block (eq. 23): lambda += rho F_ax^T (g - F_ax c)
     lxy = fmaf(rho, uxy, lxy);
     done = it + 1;
@@ -520,7 +525,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
 #pragma unroll
       for (int k = 0; k < NC; ++k) part[H_E + k] = fmaf(L.P[s][k], ep[s], part[H_E + k]);
     }
-    lp = fmaf(rho, total(reduce32(part)), lp);
+    lp = fmaf(rho, total(reduce32<NC>(part)), lp);
   }
 
   if (WPG == 2 && wv != 0) return;  // the first wave of the goal writes
