@@ -97,6 +97,57 @@ __device__ __forceinline__ int row_max_i(int v) {
 
 __device__ __forceinline__ int rdlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Wave-wide minimum / maximum of an integer, in every lane.
+__device__ __forceinline__ int wave_min_i(int v) {
+  v = row_min_i(v);
+  const auto a = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  v = min((int)a0, (int)a1);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return min((int)b0, (int)b1);
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+  v = row_max_i(v);
+  const auto a = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  const unsigned a0 = a[0], a1 = a[1];
+  v = max((int)a0, (int)a1);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  const unsigned b0 = b[0], b1 = b[1];
+  return max((int)b0, (int)b1);
+}
+
+// Wave-local LDS exchange. Values written by some lanes of a wave and read by
+// others of the same wave: the fences and the wave barrier keep the compiler from
+// moving the reads above the writes (the hardware runs one wave's LDS accesses
+// in order).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Obstacle candidate lists. A scaled obstacle state that no trajectory sample
+// reaches: (x/a - 1e30)^2 overflows to +inf, so the test q < 1 fails. A wave's
+// list holds every obstacle plus seven such entries after the last candidate, so
+// rounds of four can read the next round's entries before testing their own.
+constexpr float UNREACHABLE = 1e30f;
+constexpr int CLIST = MAX_OBS + 7;
+
+// Compacts the scaled states `ob` of the lanes with `hit` set into list[0, cnt) in
+// lane order and pads list[cnt, cnt + 7) with unreachable entries; returns cnt.
+// Every lane of the wave must take part.
+__device__ __forceinline__ int compact_candidates(bool hit, const float4& ob, float4* list) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const unsigned long long cand = __ballot(hit);
+  const int cnt = __popcll(cand);
+  if (hit) list[__builtin_amdgcn_mbcnt_hi((unsigned)(cand >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)cand, 0u))] = ob;
+  if (lane < 7) list[cnt + lane] = make_float4(UNREACHABLE, UNREACHABLE, 0.f, 0.f);
+  wave_sync_lds();
+  return cnt;
+}
+
 // Minimum over each DPP row of 16 lanes, returned in every lane of the row.
 __device__ __forceinline__ float row_min(float v) {
   v = fminf(v, dpp<DPP_QUAD_1032>(v));

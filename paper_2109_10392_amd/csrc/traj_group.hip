@@ -262,78 +262,76 @@ __device__ __forceinline__ void velocity_forms(const GConsts& K, const bool (&tv
 // Only obstacles whose box over the tile's time span, inflated by the scaled
 // half-axes plus 0.1%, meets the box of the tile's trajectory samples are
 // visited: for every other pair the scaled distance exceeds 1 in FP32 too, so the
-// result is that of visiting all obstacles.
-__device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* __restrict__ obs, int w, int lane,
-                                               const bool (&tv)[4], const float (&Tm)[4], const f4& x, const f4& y,
-                                               f4& sox, f4& soy, float& r_obs) {
+// result is that of visiting all obstacles. The boxes are compared as
+// order-preserving integer keys (single-instruction DPP minima and maxima; a
+// strict float inequality implies the same between keys), and the candidates'
+// states are compacted, in index order, into the wave's list `clist`.
+__device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* __restrict__ obs, float4* clist,
+                                               int w, int lane, const bool (&tv)[4], const float (&Tm)[4],
+                                               const f4& x, const f4& y, f4& sox, f4& soy, float& r_obs) {
+  constexpr int TOP = 0x7fffffff, BOTTOM = (int)0x80000000;
   float X[4], Y[4];
-  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+  int lxlo = TOP, lxhi = BOTTOM, lylo = TOP, lyhi = BOTTOM;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     X[r] = x[r] * K.inv_a;
     Y[r] = y[r] * K.inv_b;
-    if (tv[r]) {
-      lxlo = fminf(lxlo, X[r]);
-      lxhi = fmaxf(lxhi, X[r]);
-      lylo = fminf(lylo, Y[r]);
-      lyhi = fmaxf(lyhi, Y[r]);
-    }
+    const int kx = order_key(X[r]), ky = order_key(Y[r]);
+    lxlo = tv[r] ? min(lxlo, kx) : lxlo;
+    lxhi = tv[r] ? max(lxhi, kx) : lxhi;
+    lylo = tv[r] ? min(lylo, ky) : lylo;
+    lyhi = tv[r] ? max(lyhi, ky) : lyhi;
   }
-  const float xlo = wave_min(lxlo), xhi = wave_max(lxhi), ylo = wave_min(lylo), yhi = wave_max(lyhi);
+  const int xlo = wave_min_i(lxlo), xhi = wave_max_i(lxhi), ylo = wave_min_i(lylo), yhi = wave_max_i(lyhi);
   bool hit = false;
+  float4 ob = make_float4(UNREACHABLE, UNREACHABLE, 0.f, 0.f);
   if (lane < K.m) {
     // the scaled prediction is monotone in the sample time: its extremes over the
     // tile are at the first and last sample (same expression as below)
-    const float4 ob = obs[lane];
+    ob = obs[lane];
     const int i0 = min(TILE * w, K.n - 1), i1 = min(TILE * w + TILE - 1, K.n - 1);
     const float t0 = (float)i0 * K.dt, t1 = (float)i1 * K.dt;
     const float xa = fmaf(ob.z, t0, ob.x), xb = fmaf(ob.z, t1, ob.x);
     const float ya = fmaf(ob.w, t0, ob.y), yb = fmaf(ob.w, t1, ob.y);
     constexpr float R = 1.001f;
-    hit = (xhi > fminf(xa, xb) - R) && (xlo < fmaxf(xa, xb) + R) && (yhi > fminf(ya, yb) - R) &&
-          (ylo < fmaxf(ya, yb) + R);
+    hit = (xhi > order_key(fminf(xa, xb) - R)) & (xlo < order_key(fmaxf(xa, xb) + R)) &
+          (yhi > order_key(fminf(ya, yb) - R)) & (ylo < order_key(fmaxf(ya, yb) + R));
   }
-  unsigned long long cand = __ballot(hit);
+  const int cnt = compact_candidates(hit, ob, clist);
   float Sx[4] = {0.f, 0.f, 0.f, 0.f}, Sy[4] = {0.f, 0.f, 0.f, 0.f};
-  while (cand) {
-    // up to four candidates per round, their LDS reads issued together
-    int jj[4];
+  auto test1 = [&](const float4& o) {
+    float tx[4], ty[4], qq[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      jj[u] = cand ? __builtin_ctzll(cand) : -1;
-      cand &= cand - 1;
+    for (int r = 0; r < 4; ++r) {
+      tx[r] = X[r] - fmaf(o.z, Tm[r], o.x);
+      ty[r] = Y[r] - fmaf(o.w, Tm[r], o.y);
+      qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
     }
-    float4 ob[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) ob[u] = obs[jj[u] < 0 ? 0 : jj[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (jj[u] < 0) break;
-      float tx[4], ty[4], qq[4];
+    if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        tx[r] = X[r] - fmaf(ob[u].z, Tm[r], ob[u].x);
-        ty[r] = Y[r] - fmaf(ob[u].w, Tm[r], ob[u].y);
-        qq[r] = tv[r] ? fmaf(tx[r], tx[r], ty[r] * ty[r]) : 2.f;
-      }
-      if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (qq[r] < 1.f) {
-            if (qq[r] > 0.f) {
-              const float f = rsqrtf(qq[r]) - 1.f;
-              Sx[r] = fmaf(tx[r], f, Sx[r]);
-              Sy[r] = fmaf(ty[r], f, Sy[r]);
-              r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, r_obs);
-            } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
-              Sx[r] += 1.f;
-              r_obs += K.a2;
-            }
+        if (qq[r] < 1.f) {
+          if (qq[r] > 0.f) {
+            const float f = rsqrtf(qq[r]) - 1.f;
+            Sx[r] = fmaf(tx[r], f, Sx[r]);
+            Sy[r] = fmaf(ty[r], f, Sy[r]);
+            r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, r_obs);
+          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
+            Sx[r] += 1.f;
+            r_obs += K.a2;
           }
         }
       }
     }
+  };
+  // rounds of two, their reads issued together (the padding keeps them in the list)
+  for (int c0 = 0; c0 < cnt; c0 += 2) {
+    const float4 o0 = clist[c0], o1 = clist[c0 + 1];
+    test1(o0);
+    test1(o1);
   }
+  // the list is rewritten by the next tile: every lane's reads first
+  wave_sync_lds();
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     sox[r] = K.a * Sx[r];
@@ -343,7 +341,7 @@ __device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* _
 
 template <int MODE>
 __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm, int G, int scene, int pos0,
-                            int n_solved, int lane, float4* sobs, float4* sth, double* sc0) {
+                            int n_solved, int lane, float4* sobs, float4* sth, double* sc0, float4* clist) {
   const int j = lane & 15, q = lane >> 4;
   const int NG = A.n_goals;
   int s0, s1;
@@ -595,7 +593,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
           op[3] = nxt[3 * WAVE];
         }
         f4 sox, soy;
-        obstacle_forms(K, obs, w, lane, tv, Tm, x, y, sox, soy, racc[0]);
+        obstacle_forms(K, obs, clist, w, lane, tv, Tm, x, y, sox, soy, racc[0]);
         ux = contract<MODE>(ct, sox, ux);
         uy = contract<MODE>(ct, soy, uy);
       }
@@ -712,6 +710,7 @@ __device__ __forceinline__ int claim(int32_t* header) {
 template <int MODE>
 __global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A, GroupArgs L) {
   __shared__ float4 sobs[GROUP_WAVES][MAX_OBS];           // each wave's current scene's obstacles (scaled)
+  __shared__ float4 sclist[GROUP_WAVES][CLIST];           // each wave's obstacle candidates of a tile
   __shared__ float4 sth[GROUP_WAVES][MAX_TILES * WAVE];    // each wave's theta at its lanes' samples
   __shared__ double sc0[GROUP_WAVES][2 * 4 * WAVE];  // each wave's particular parts of the x/y step (FP64 in
                                                      // the FP32 form, FP32 in the split form)
@@ -722,7 +721,7 @@ __global__ __launch_bounds__(WAVE * GROUP_WAVES, 2) void k_am_group(SolveArgs A,
   while (idx < n_items) {
     const int2 it = L.items[idx];
     solve_group<MODE>(A, L.perm, scene_group(A, L, it.x), it.x, it.y, L.nvalid[it.x], lane, sobs[wv], sth[wv],
-                      sc0[wv]);
+                      sc0[wv], sclist[wv]);
     idx = L.persistent ? claim(L.header) : n_items;
   }
 }

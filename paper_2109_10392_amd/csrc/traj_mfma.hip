@@ -111,19 +111,21 @@ __device__ __forceinline__ void samples(const Consts& K, const float2* __restric
                                         SampleOut& o) {
   bool tv[4];
   float X[4], Y[4];
-  float lxlo = __builtin_inff(), lxhi = -__builtin_inff(), lylo = __builtin_inff(), lyhi = -__builtin_inff();
+  // the tile's box as order-preserving integer keys (single-instruction DPP
+  // minima and maxima; a strict float inequality implies the same between keys)
+  constexpr int TOP = 0x7fffffff, BOTTOM = (int)0x80000000;
+  int lxlo = TOP, lxhi = BOTTOM, lylo = TOP, lyhi = BOTTOM;
   o.r_obs = o.r_acc = o.r_nh = o.r_psi = 0.f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     tv[r] = gv && (TILE * w + 4 * q + r) < K.n;
     X[r] = x[r] * K.inv_a;
     Y[r] = y[r] * K.inv_b;
-    if (tv[r]) {
-      lxlo = fminf(lxlo, X[r]);
-      lxhi = fmaxf(lxhi, X[r]);
-      lylo = fminf(lylo, Y[r]);
-      lyhi = fmaxf(lyhi, Y[r]);
-    }
+    const int kx = order_key(X[r]), ky = order_key(Y[r]);
+    lxlo = tv[r] ? min(lxlo, kx) : lxlo;
+    lxhi = tv[r] ? max(lxhi, kx) : lxhi;
+    lylo = tv[r] ? min(lylo, ky) : lylo;
+    lyhi = tv[r] ? max(lyhi, ky) : lyhi;
     // velocity (eq. 21), heading direction, z - x'
     const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
     float sn, cs;
@@ -147,11 +149,11 @@ __device__ __forceinline__ void samples(const Consts& K, const float2* __restric
   }
   // obstacle polar variables (eqs. 15, 22) with exact culling against the
   // tile's obstacle boxes (inflated by the scaled half-axes + 0.1%)
-  const float xlo = wave_min(lxlo), xhi = wave_max(lxhi), ylo = wave_min(lylo), yhi = wave_max(lyhi);
+  const int xlo = wave_min_i(lxlo), xhi = wave_max_i(lxhi), ylo = wave_min_i(lylo), yhi = wave_max_i(lyhi);
   bool hit = false;
   if (lane < K.m) {
     const float4 bx = box[w * K.m + lane];
-    hit = (xhi > bx.x) && (xlo < bx.y) && (yhi > bx.z) && (ylo < bx.w);
+    hit = (xhi > order_key(bx.x)) & (xlo < order_key(bx.y)) & (yhi > order_key(bx.z)) & (ylo < order_key(bx.w));
   }
   unsigned long long cand = __ballot(hit);
   float Sx[4] = {0.f, 0.f, 0.f, 0.f}, Sy[4] = {0.f, 0.f, 0.f, 0.f};

@@ -70,16 +70,6 @@ __device__ __forceinline__ float pair_sum(float v, float* ex, int& buf) {
   return r;
 }
 
-// Wave-local LDS exchange. Values written by some lanes of a wave and read by
-// others of the same wave: the fences and the wave barrier keep the compiler from
-// moving the reads above the writes (the hardware runs one wave's LDS accesses
-// in order).
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // The home lanes' values of one coefficient vector: lane 2k (k < NC) holds value k
 // of the lower set, lane 32 + 2k value k of the upper set. They are written to the
 // wave's slot (lower set at [0, 16), upper set at [16, 32)).
@@ -134,12 +124,6 @@ struct Lane {
   int4 box[S][WAVE / 16];  // order keys of the box (x low, x high, y low, y high)
   bool val[S];
 };
-
-// Scaled obstacle state that no trajectory sample reaches: (x/a - 1e30)^2
-// overflows to +inf, so the test q < 1 fails.
-constexpr float UNREACHABLE = 1e30f;
-// Entries of a wave's candidate list: every obstacle plus seven padding entries.
-constexpr int CLIST = MAX_OBS + 7;
 
 __device__ __forceinline__ float dotc(const float (&r)[NC], const float (&c)[NC]) {
   float acc = 0.f;
@@ -227,15 +211,8 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
       const int4 bx = L.box[s][rw];
       hit = hit | ((rxh > bx.x) & (rxl < bx.y) & (ryh > bx.z) & (ryl < bx.w));
     }
-    // The candidates' scaled states, compacted in index order into the wave's
-    // list and followed by seven unreachable entries, so that rounds of four read
-    // the next round's entries before testing their own without a bound check.
-    hit = hit && lane < G.m;
-    const unsigned long long cand = __ballot(hit);
-    const int cnt = __popcll(cand);
-    if (hit) clist[__builtin_amdgcn_mbcnt_hi((unsigned)(cand >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)cand, 0u))] = L.ob;
-    if (lane < 7) clist[cnt + lane] = make_float4(UNREACHABLE, UNREACHABLE, 0.f, 0.f);
-    wave_sync_lds();
+    // the candidates' scaled states, compacted in index order into the wave's list
+    const int cnt = compact_candidates(hit && lane < G.m, L.ob, clist);
     const float tm = L.tm[s];
     float Sx = 0.f, Sy = 0.f, ro = 0.f;
     auto test4 = [&](const float4 (&o)[4]) {
