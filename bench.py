@@ -35,13 +35,13 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.65  # the same without packed FP32, which this li
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "10dcc7f676c08d526918c802b23f52bfee0f924b0dbb8327b32116ae2ef30499",
-              "bytes_per_launch": int((244.5 * 2.0 + 284.0) * 1024),
+              "sha256": "2f833caa3f218bdb83bac50e2e2ef97100b62b2cb930ebe17a7120366f41cec8",
+              "bytes_per_launch": int((245.0 * 2.0 + 284.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "d12d6a33f22df64276589864c7dc72a4c0c50bd08336d2ce9f26f166e26a8532",
-               "bytes_per_launch": int((83161.9 * 2.0 + 278148.0) * 1024),
+               "sha256": "c3c86e37bb36018d2be48210e2a045ca9b93a5e1e6a08cf1676bc0c88fa5a438",
+               "bytes_per_launch": int((77901.6 * 2.0 + 277296.6) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
