@@ -267,22 +267,44 @@ __global__ void k_sync_bf16(const float* __restrict__ p, uint16_t* __restrict__ 
   if (i < n) pb[i] = f2bf(p[i]);
 }
 
-__global__ void k_colstats(const float* __restrict__ rows, int n_rows, int n_cols, float* __restrict__ mean,
-                           float* __restrict__ stdv) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cols) return;
+// Column mean and deviation (FP64 sums, fixed order): a workgroup takes 64
+// columns; its 16 waves sum the rows r = slice (mod 16), and the partial sums are
+// added in slice order, first for the mean, then for the squared deviations.
+__global__ __launch_bounds__(WAVE * COLSUM_SLICES) void k_colstats(const float* __restrict__ rows, int n_rows,
+                                                                   int n_cols, float* __restrict__ mean,
+                                                                   float* __restrict__ stdv) {
+  __shared__ double part[COLSUM_SLICES][WAVE];
+  __shared__ double mu_s[WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), sl = threadIdx.x / WAVE;
+  const int c = blockIdx.x * WAVE + lane;
   double s = 0.0;
-  for (int r = 0; r < n_rows; ++r) s += rows[(size_t)r * n_cols + c];
-  const double mu = s / n_rows;
-  double q = 0.0;
-  for (int r = 0; r < n_rows; ++r) {
-    const double d = rows[(size_t)r * n_cols + c] - mu;
-    q += d * d;
+  if (c < n_cols)
+    for (int r = sl; r < n_rows; r += COLSUM_SLICES) s += rows[(size_t)r * n_cols + c];
+  part[sl][lane] = s;
+  __syncthreads();
+  if (sl == 0) {
+    double t = 0.0;
+    for (int i = 0; i < COLSUM_SLICES; ++i) t += part[i][lane];
+    mu_s[lane] = t / n_rows;
   }
-  double sd = sqrt(q / n_rows);
-  if (sd < 1e-5 * fmax(1.0, fabs(mu))) sd = 1.0;
-  mean[c] = (float)mu;
-  stdv[c] = (float)sd;
+  __syncthreads();
+  const double mu = mu_s[lane];
+  double q = 0.0;
+  if (c < n_cols)
+    for (int r = sl; r < n_rows; r += COLSUM_SLICES) {
+      const double d = rows[(size_t)r * n_cols + c] - mu;
+      q += d * d;
+    }
+  part[sl][lane] = q;  // every read of the first pass's sums came before the barrier above
+  __syncthreads();
+  if (sl == 0 && c < n_cols) {
+    double t = 0.0;
+    for (int i = 0; i < COLSUM_SLICES; ++i) t += part[i][lane];
+    double sd = sqrt(t / n_rows);
+    if (sd < 1e-5 * fmax(1.0, fabs(mu))) sd = 1.0;
+    mean[c] = (float)mu;
+    stdv[c] = (float)sd;
+  }
 }
 
 // state <-> rows: thread per (scene, goal slot, value)
@@ -503,8 +525,8 @@ int traj_mlp_adam(const traj_mlp* net, int step, float lr, float beta1, float be
 int traj_colstats(const float* rows, int n_rows, int n_cols, float* mean, float* stdv, void* stream) {
   if (!rows || !mean || !stdv || n_rows < 1 || n_cols < 0) return traj::api_fail(TRAJ_E_INVAL, "traj_colstats: bad arguments");
   if (n_cols == 0) return TRAJ_OK;
-  hipLaunchKernelGGL(k_colstats, dim3(blocks_for(n_cols, 256)), dim3(256), 0, (hipStream_t)stream, rows, n_rows, n_cols,
-                     mean, stdv);
+  hipLaunchKernelGGL(k_colstats, dim3(blocks_for(n_cols, WAVE)), dim3(WAVE * COLSUM_SLICES), 0, (hipStream_t)stream,
+                     rows, n_rows, n_cols, mean, stdv);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? TRAJ_OK : traj::api_fail(TRAJ_E_HIP, "traj_colstats: %s", hipGetErrorString(e));
 }
