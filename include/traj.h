@@ -296,8 +296,9 @@ int traj_work_ints(void *handle, int n_scenes, int n_goals, int64_t *out);
  * this handle may be running (synchronise its streams first). Raising the
  * smallest group size never invalidates a work buffer sized before; lowering it
  * can (traj_work_ints).
- * Errors: TRAJ_E_INVAL (NULL handle or out, a size outside 0..16; nothing is
- * changed), TRAJ_E_HIP.
+ * The current device must be the one the handle was set up on.
+ * Errors: TRAJ_E_INVAL (NULL handle or out, a size outside 0..16, another
+ * current device; nothing is changed), TRAJ_E_HIP.
  */
 int traj_set_shape_groups(void *handle, const int32_t *groups);
 int traj_get_shape_groups(void *handle, int32_t *groups);

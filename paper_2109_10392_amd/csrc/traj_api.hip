@@ -513,6 +513,11 @@ int traj_set_shape_groups(void* handle, const int32_t* groups) {
   g_err.clear();
   Handle* h = (Handle*)handle;
   if (h == nullptr) return fail(TRAJ_E_INVAL, "NULL handle");
+  int cur = -1;
+  const hipError_t ed = hipGetDevice(&cur);
+  if (ed != hipSuccess) return hip_fail(ed, "traj_set_shape_groups: current device");
+  if (cur != h->device)
+    return fail(TRAJ_E_INVAL, "traj_set_shape_groups: current device %d is not the handle's device %d", cur, h->device);
   std::vector<ShapeDesc> next = h->shapes;
   for (size_t i = 0; i < next.size(); ++i) {
     const int g = groups == nullptr ? 0 : groups[i];
