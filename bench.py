@@ -345,6 +345,9 @@ def main():
     ap.add_argument("--clear-min", type=float, default=1.0,
                     help="mpc: collision post-check of the ranking (scaled obstacle distance; 0 = off)")
     ap.add_argument("--no-warm", action="store_true", help="dense: skip the reduced warm-start leg")
+    ap.add_argument("--obstacle-range", type=float, default=80.0,
+                    help="dense: obstacles placed over [0, L] m (80: the benchmark; 266.7: the 11-goal scenes' "
+                         "density, the sensitivity variant)")
     ap.add_argument("--warm-train", type=int, default=20000, help="dense: training scenes of the warm-start leg")
     ap.add_argument("--warm-test", type=int, default=2048, help="dense: held-out scenes of the warm-start leg")
     ap.add_argument("--warm-epochs", type=int, default=30, help="dense: training epochs of the warm-start leg")
@@ -371,13 +374,15 @@ def main():
     # the CPU oracle first, before anything initialises the GPU (its workers are new processes)
     cpu = cpu_baseline(args.seed, args.iters, args.cpu_goals) if not args.no_cpu and args.workload == "dense" else None
 
+    import numpy as np
     import torch
 
     from paper_2109_10392_amd import scenes as S
     from paper_2109_10392_amd import traj as T
 
     torch.cuda.set_device(0)
-    batch = S.workload_dense(args.seed) if args.workload == "dense" else S.workload_uneven(args.seed)
+    x_range = (0.0, args.obstacle_range)
+    batch = S.workload_dense(args.seed, x_range) if args.workload == "dense" else S.workload_uneven(args.seed)
     sc = batch.scenes[0]
     n, m, B = sc.n_time, sc.obs.shape[0], batch.n_goals
     solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
@@ -457,8 +462,10 @@ def main():
         "dtype": "f32+f64" if args.precision == "fp32" else "bf16x3+f32+f64",
         "data": "synthetic",
         "config": ({"workload": "dense highway scene: 1 scene x 1024 goals, 50 obstacles, 6 lanes, "
-                                "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring",
-                    "goals": B, "obstacles": m, "n_time": n}
+                                "T=100 over 10 s, Bernstein-10 basis, 100 AM iterations (cold start) + scoring"
+                                + ("" if args.obstacle_range == 80.0 else
+                                   f"; obstacles placed over {args.obstacle_range:.0f} m"),
+                    "goals": B, "obstacles": m, "n_time": n, "obstacle_range_m": args.obstacle_range}
                    if args.workload == "dense" else
                    {"workload": "uneven batch: 512 scenes, goals log-uniform 16-1024, obstacles U{4..64}, "
                                 "T in {50,100,150}, 100 AM iterations (cold start) + scoring",
@@ -467,9 +474,12 @@ def main():
            "waves": waves} | ({"bucket_groups": buckets} if buckets else {}),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(args.workload, kernel, waves, args.precision),
+                     "traffic": (measured_traffic(args.workload, kernel, waves, args.precision)
+                                 if args.obstacle_range == 80.0 else None),
                      "kernel": {"wave": "k_am (wave kernel)", "mfma": "k_am_mfma", "group": "k_am_group"}[kernel],
                      "kernel_ms": solve_avg_s * 1e3,
+                     "kernel_ms_p10_median_p90": [float(np.percentile(solve_ms, 10)), float(np.median(solve_ms)),
+                                                  float(np.percentile(solve_ms, 90))],
                      "algorithmic_flop_per_launch": flops,
                      "frac_without_obstacle_tests": flops_no_obs / solve_avg_s / 1e12 / PEAK_FP32_TFLOPS,
                      "frac_of_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED_TFLOPS,

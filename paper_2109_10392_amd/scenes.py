@@ -202,9 +202,17 @@ def workload_small(seed: int) -> Batch:
     return Batch([make_scene(seed, n_goals=11, n_obs=10, n_lanes=4, n_time=100, t_f=10.0)])
 
 
-def workload_dense(seed: int) -> Batch:
-    """1 scene x 1024 goals, 50 obstacles, 6 lanes, T = 100 over 10 s."""
-    return Batch([make_scene(seed, n_goals=1024, n_obs=50, n_lanes=6, n_time=100, t_f=10.0)])
+# Obstacle placement range of the dense scene's density-sensitivity variant: the
+# 11-goal scenes' density (10 obstacles over 4 lanes x 80 m) with 50 obstacles on
+# 6 lanes, 80 * (50 / 10) * (4 / 6) m.
+SPARSE_DENSE_RANGE = (0.0, 80.0 * (50 / 10) * (4 / 6))
+
+
+def workload_dense(seed: int, x_range=(0.0, 80.0)) -> Batch:
+    """1 scene x 1024 goals, 50 obstacles, 6 lanes, T = 100 over 10 s; obstacles
+    placed over x_range (the default is the 11-goal scenes' 0-80 m, so five times
+    their density per lane x 4/6; SPARSE_DENSE_RANGE keeps their density)."""
+    return Batch([make_scene(seed, n_goals=1024, n_obs=50, n_lanes=6, n_time=100, t_f=10.0, x_range=x_range)])
 
 
 def workload_uneven(seed: int = 0, n_scenes: int = 512, lo: int = 16, hi: int = 1024) -> Batch:

@@ -59,6 +59,18 @@ def test_two_waves_dense(T, seed):
     assert np.all(np.isfinite(out["c"])) and np.all(np.isfinite(out["resid"]))
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_two_waves_dense_at_the_small_scenes_density(T, seed):
+    """The dense scene's density-sensitivity variant (50 obstacles spread over
+    267 m, the 11-goal scenes' density) in the benchmark's launch: 128 goals
+    spread over the scene."""
+    batch = S.workload_dense(seed, x_range=S.SPARSE_DENSE_RANGE)
+    out = gpu_solve(T, batch, 100, kernel="wave", waves=2)
+    goals = list(range(seed % 8, 1024, 8))
+    print(f"dense seed {seed} at the small scenes' density, {len(goals)} goals:")
+    gate_batch(T, batch, 100, out, goals={0: goals}, kernel="wave", waves=2)
+
+
 def test_two_waves_ragged(T):
     batch = ragged_batch()
     out = gpu_solve(T, batch, 40, kernel="wave", waves=2)
