@@ -1,7 +1,8 @@
 """traj_solve_batch_noalloc (the group kernel's work list in the library's own
 device scratch) against traj_solve_batch with a caller-owned work buffer, through
 the C-ABI: bitwise equal results on two calls in a row, the second on a smaller
-batch, and the size limit rejected before any device work."""
+batch, with per-shape group sizes too, and the size limit rejected before any
+device work."""
 import ctypes
 
 import numpy as np
@@ -73,6 +74,24 @@ def test_noalloc_small_group_size_and_listed_schedule(T):
     solver = T.Solver(PARAMS, sorted(set(big.shapes()) | set(small.shapes())))
     try:
         solver.set_tile("group", 3, False)
+        for batch in (big, small):
+            ref = _run(T, solver, batch, 20, noalloc=False)
+            out = _run(T, solver, batch, 20, noalloc=True)
+            for k in ("c", "lam", "resid", "iters"):
+                assert np.array_equal(out[k], ref[k], equal_nan=True), k
+    finally:
+        solver.close()
+
+
+def test_noalloc_with_per_shape_group_sizes(T):
+    """Group sizes set per shape (traj_set_shape_groups): the scratch list is sized
+    by the smallest, and the results equal the caller-owned buffer's."""
+    big, small = _batches()
+    shapes = sorted(set(big.shapes()) | set(small.shapes()))
+    solver = T.Solver(PARAMS, shapes)
+    try:
+        solver.set_tile("group", 16, True)
+        solver.set_shape_groups([(2, 5, 0, 11, 7, 3)[i % 6] for i in range(len(shapes))])
         for batch in (big, small):
             ref = _run(T, solver, batch, 20, noalloc=False)
             out = _run(T, solver, batch, 20, noalloc=True)
