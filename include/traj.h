@@ -41,7 +41,8 @@ extern "C" {
 #define TRAJ_INIT_FROM_STATE 0x1u /* start from (c, lam) in the state (resume, warm start)   */
 #define TRAJ_WARM_FALLBACK 0x2u   /* with FROM_STATE, group kernel: the first iteration also
                                      runs from the cold start; each goal keeps whichever has
-                                     the lower max(r_obs, r_acc, r_nh) after it               */
+                                     the lower max(r_obs, r_acc, r_nh) after it (a NaN
+                                     component makes the given state's residual lose)    */
 #define TRAJ_KEEP_DONE 0x4u       /* traj_converge only: scene_done and scene_iters are kept, not
                                      reset; scenes already done are left untouched and the
                                      others start as the other flags say                      */

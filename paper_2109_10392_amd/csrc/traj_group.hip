@@ -623,7 +623,7 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
   };
   // max(r_obs, r_acc, r_nh) of the lane's goal at the last projection sweep
   auto worst_resid = [&]() {
-    return sqrtf(fmaxf(fmaxf(sum_rows(racc[0]), sum_rows(racc[1])), sum_rows(racc[2])));
+    return sqrtf(worst_of(sum_rows(racc[0]), sum_rows(racc[1]), sum_rows(racc[2])));
   };
   auto store_state = [&]() {
     if (!gv) return;

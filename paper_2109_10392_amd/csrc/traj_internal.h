@@ -46,6 +46,15 @@ constexpr int BND_SIZE = BND_M0BY + NC * NY;
 constexpr int TILE_T = 16;
 constexpr int PACK_SLOTS = 6;
 __host__ __device__ inline int n_tiles(int n) { return (n + TILE_T - 1) / TILE_T; }
+
+// max(r_obs, r_acc, r_nh) (squared or not) of the stopping rule and of the warm
+// start's fallback test; NaN when any component is NaN, which fmaxf alone would
+// drop (a goal with NaN coefficients has r_obs = 0: no inside test holds).
+__host__ __device__ inline float worst_of(float a, float b, float c) {
+  const float m = fmaxf(fmaxf(a, b), c);
+  const float s = a + b + c;  // the components are >= 0: NaN exactly when one is NaN
+  return s == s ? m : __builtin_nanf("");
+}
 __host__ __device__ inline int tab_pack(int n) { return (tab_bnd(n) + BND_SIZE + 3) & ~3; }
 __host__ __device__ inline int tab_size(int n) { return tab_pack(n) + n_tiles(n) * PACK_SLOTS * WAVE * 4; }
 

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
       f4 rr;
       residuals(rr);
       // every goal of the group below tol (the group advances together)
-      const float worst = sqrtf(fmaxf(fmaxf(rr[0], rr[1]), rr[2]));
+      const float worst = sqrtf(worst_of(rr[0], rr[1], rr[2]));
       const bool ok = !gv || worst <= A.tol;
       if (__ballot(!ok) == 0ull) {
         stopped = true;

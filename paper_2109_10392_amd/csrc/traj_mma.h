@@ -319,6 +319,10 @@ __device__ __forceinline__ void particular(const float* __restrict__ T, const do
     P.c0x[r] = 0.f;
     P.c0y[r] = 0.f;
     P.c0p[r] = 0.f;
+    if (cold) {  // the padding rows k >= NC too: an apply multiplies them by zero operator
+      cx[r] = 0.f;  // columns, which a NaN or infinity left there would turn into NaN
+      cy[r] = 0.f;
+    }
     if (k < NC) {
       if constexpr (MODE == TRAJ_MODE_FP32) {
         double sx = 0.0, sy = 0.0;

@@ -178,8 +178,8 @@ __global__ __launch_bounds__(SCORE_THREADS) void k_argmin(ScoreArgs A, ConvergeC
       C.scene_iters[s] += C.iters;
       const int g = g0 + b;
       if (b >= 0 && g < A.n_goals) {
-        const float worst = fmaxf(fmaxf(C.resid[0 * A.n_goals + g], C.resid[1 * A.n_goals + g]),
-                                  C.resid[2 * A.n_goals + g]);
+        const float worst =
+            worst_of(C.resid[0 * A.n_goals + g], C.resid[1 * A.n_goals + g], C.resid[2 * A.n_goals + g]);
         if (worst <= C.tol) C.done[s] = 1;
       }
     }

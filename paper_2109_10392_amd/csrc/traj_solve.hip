@@ -489,7 +489,7 @@ __device__ void solve_goal(const SolveArgs& A, const ShapeDesc& sd, const float*
     lxy = fmaf(rho, uxy, lxy);
     done = it + 1;
     if (A.tol > 0.f && done % 5 == 0) {
-      const float worst = fmaxf(fmaxf(rdlane(uxy, 2 * R_OBS), rdlane(uxy, 2 * R_ACC)), rdlane(uxy, 2 * R_NH));
+      const float worst = worst_of(rdlane(uxy, 2 * R_OBS), rdlane(uxy, 2 * R_ACC), rdlane(uxy, 2 * R_NH));
       if (sqrtf(worst) <= A.tol) break;
     }
   }

@@ -130,13 +130,24 @@ def test_converge_stops_at_the_first_chunk_meeting_the_rule(T, kernel, waves, pr
     solver.close()
 
 
-def test_warm_fallback_keeps_the_better_start_per_goal(T):
+@pytest.mark.parametrize("bad", ["far", "nan", "huge"])
+def test_warm_fallback_keeps_the_better_start_per_goal(T, bad):
+    """Every third goal starts from a corrupted state (values of order 1e3, NaN,
+    or 1e30 whose products overflow): those goals end exactly where the cold start
+    ends, the others exactly where the plain warm start does."""
     batch = small_batch()
     n = batch.n_goals
     good = run(T, batch, 150)                      # near the fixed point: warm wins
     rng = np.random.default_rng(0)
-    bad_c = rng.normal(0, 1e3, (3, 11, n)).astype(np.float32)
-    bad_l = rng.normal(0, 1e3, (3, 11, n)).astype(np.float32)
+    if bad == "far":
+        bad_c = rng.normal(0, 1e3, (3, 11, n)).astype(np.float32)
+        bad_l = rng.normal(0, 1e3, (3, 11, n)).astype(np.float32)
+    elif bad == "nan":
+        bad_c = np.full((3, 11, n), np.nan, np.float32)
+        bad_l = rng.normal(0, 1.0, (3, 11, n)).astype(np.float32)
+    else:
+        bad_c = np.full((3, 11, n), 1e30, np.float32)
+        bad_l = np.full((3, 11, n), -1e30, np.float32)
     use_good = (np.arange(n) % 3) != 0
     init_c = np.where(use_good[None, None], good[0], bad_c)
     init_l = np.where(use_good[None, None], good[1], bad_l)
