@@ -515,6 +515,43 @@ def test_score_matches_oracle(T):
     solver.close()
 
 
+def test_every_goal_filtered_gives_no_best_goal(T):
+    """With a heading bound no trajectory keeps (psi_max = 1e-6 rad against an
+    initial heading of 0.01 rad; the filter of Sec. III, assumption 2), every
+    goal's cost is +inf, as the oracle's, the best goal is -1, and a chunked solve
+    never marks the scene converged: it runs to max_iters."""
+    import torch
+    params = dict(PARAMS, psi_max=1e-6)
+    scenes = [S.workload_small(1).scenes[0], S.make_scene(9, 16, 10)]
+    for sc in scenes:
+        sc.ego[6] = 0.01  # initial heading (eq. 8b): |psi(0)| = 0.01 > psi_max on every goal
+    batch = S.Batch(scenes)
+    solver = T.Solver(params, batch.shapes())
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    solver.solve(db, st, 20)
+    v_ref = torch.tensor([float(sc.ego[2]) for sc in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    solver.score(db, st, v_ref, cost, best)
+    torch.cuda.synchronize()
+    c = st.c.cpu().numpy().astype(np.float64)
+    off = batch.goal_off()
+    for i, sc in enumerate(batch.scenes):
+        prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], params)
+        sl = slice(off[i], off[i + 1])
+        ref = O.meta_cost(prob, c[0][:, sl], c[1][:, sl], c[2][:, sl], 0, v_ref=float(sc.ego[2]))
+        assert np.all(np.isinf(ref)) and O.best_goal(ref) == -1
+    assert np.all(np.isinf(cost.cpu().numpy())) and np.all(best.cpu().numpy() == -1)
+    st2 = T.DeviceState.empty(batch.n_goals)
+    iters = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    solver.converge(db, st2, v_ref, cost, best, iters, max_iters=30, chunk=5, tol=1e-3)
+    torch.cuda.synchronize()
+    assert np.all(st2.scene_done.cpu().numpy()[:batch.n_scenes] == 0)
+    assert np.all(iters.cpu().numpy() == 30) and np.all(best.cpu().numpy() == -1)
+    solver.close()
+
+
 @pytest.mark.parametrize("tile", [("wave", 1, 192), ("wave", 2, 192), ("group", 1, 192), ("mfma", 1, 176)])
 def test_largest_horizon_and_obstacle_count(T, tile):
     """The largest shape each kernel takes with 64 obstacles against the oracle:
