@@ -515,6 +515,35 @@ def test_score_matches_oracle(T):
     solver.close()
 
 
+@pytest.mark.parametrize("kernel,waves", [("wave", 1), ("wave", 2), ("mfma", 1), ("group", 1)])
+def test_a_scene_without_goals_changes_nothing(T, kernel, waves):
+    """A scene with no goals in the middle of a batch: the other scenes' results are
+    bitwise those of the batch without it, its best goal is -1, and a chunked
+    solve leaves it unconverged."""
+    import torch
+    a, b = S.make_scene(41, 9, 10, n_lanes=4), S.make_scene(42, 13, 5, n_lanes=6, n_time=60, t_f=6.0)
+    empty = S.make_scene(43, 0, 10, n_lanes=4)
+    with_empty, without = S.Batch([a, empty, b]), S.Batch([a, b])
+    shapes = sorted(set(with_empty.shapes()))
+    ref = gpu_solve(T, without, 25, shapes=shapes, kernel=kernel, waves=waves)
+    out = gpu_solve(T, with_empty, 25, shapes=shapes, kernel=kernel, waves=waves)
+    for k in ("c", "lam", "resid"):
+        assert np.array_equal(out[k], ref[k]), k
+    solver = T.Solver(PARAMS, shapes)
+    solver.set_tile(kernel, 16, True, waves)
+    db = T.DeviceBatch.from_batch(with_empty, shapes=shapes)
+    st = T.DeviceState.empty(with_empty.n_goals)
+    v_ref = torch.tensor([float(sc.ego[2]) for sc in with_empty.scenes], device="cuda")
+    cost = torch.zeros(with_empty.n_goals, device="cuda")
+    best = torch.zeros(3, device="cuda", dtype=torch.int32)
+    iters = torch.zeros(3, device="cuda", dtype=torch.int32)
+    solver.converge(db, st, v_ref, cost, best, iters, max_iters=20, chunk=5, tol=1e-3)
+    torch.cuda.synchronize()
+    assert int(best[1].item()) == -1 and int(st.scene_done[1].item()) == 0 and int(iters[1].item()) == 20
+    assert int(best[0].item()) >= 0 and int(best[2].item()) >= 0
+    solver.close()
+
+
 def test_every_goal_filtered_gives_no_best_goal(T):
     """With a heading bound no trajectory keeps (psi_max = 1e-6 rad against an
     initial heading of 0.01 rad; the filter of Sec. III, assumption 2), every
