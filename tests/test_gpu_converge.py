@@ -33,7 +33,7 @@ def small_batch():
                     enumerate([(11, 10), (7, 4), (16, 10), (3, 0), (20, 12)])])
 
 
-def run(T, batch, iters, kernel="group", init=None, fallback=False, skip=None):
+def run(T, batch, iters, kernel="group", init=None, fallback=False, skip=None, precision="fp32"):
     import torch
     solver = T.Solver(PARAMS, batch.shapes())
     solver.set_tile(kernel, 16, True)
@@ -44,7 +44,7 @@ def run(T, batch, iters, kernel="group", init=None, fallback=False, skip=None):
         st.lam.copy_(torch.as_tensor(init[1], device="cuda"))
     if skip is not None:
         st.scene_done = torch.as_tensor(np.asarray(skip, np.int32), device="cuda")
-    solver.solve(db, st, iters, from_state=init is not None, fallback=fallback)
+    solver.solve(db, st, iters, from_state=init is not None, fallback=fallback, precision=precision)
     torch.cuda.synchronize()
     out = (st.c.cpu().numpy(), st.lam.cpu().numpy(), st.resid.cpu().numpy())
     solver.close()
@@ -130,8 +130,9 @@ def test_converge_stops_at_the_first_chunk_meeting_the_rule(T, kernel, waves, pr
     solver.close()
 
 
-@pytest.mark.parametrize("bad", ["far", "nan", "huge"])
-def test_warm_fallback_keeps_the_better_start_per_goal(T, bad):
+@pytest.mark.parametrize("bad,precision", [("far", "fp32"), ("nan", "fp32"), ("huge", "fp32"), ("nan", "bf16x3"),
+                                           ("huge", "bf16x3")])
+def test_warm_fallback_keeps_the_better_start_per_goal(T, bad, precision):
     """Every third goal starts from a corrupted state (values of order 1e3, NaN,
     or 1e30 whose products overflow): those goals end exactly where the cold start
     ends, the others exactly where the plain warm start does."""
@@ -151,9 +152,9 @@ def test_warm_fallback_keeps_the_better_start_per_goal(T, bad):
     use_good = (np.arange(n) % 3) != 0
     init_c = np.where(use_good[None, None], good[0], bad_c)
     init_l = np.where(use_good[None, None], good[1], bad_l)
-    got = run(T, batch, 25, init=(init_c, init_l), fallback=True)
-    warm = run(T, batch, 25, init=(init_c, init_l))
-    cold = run(T, batch, 25)
+    got = run(T, batch, 25, init=(init_c, init_l), fallback=True, precision=precision)
+    warm = run(T, batch, 25, init=(init_c, init_l), precision=precision)
+    cold = run(T, batch, 25, precision=precision)
     for g in range(n):
         ref = warm if use_good[g] else cold
         assert np.array_equal(got[0][:, :, g], ref[0][:, :, g]), g
