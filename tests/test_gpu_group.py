@@ -111,11 +111,12 @@ def test_per_shape_group_sizes_do_not_change_results(T, precision):
     solver.close()
 
 
-def test_group_resume_equals_continuous_bitwise(T):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_group_resume_equals_continuous_bitwise(T, precision):
     batch = S.workload_small(5)
-    full = gpu_solve(T, batch, 100, kernel="group")
-    part = gpu_solve(T, batch, 40, kernel="group")
-    rest = gpu_solve(T, batch, 60, init=dict(c=part["c"], lam=part["lam"]), kernel="group")
+    full = gpu_solve(T, batch, 100, kernel="group", precision=precision)
+    part = gpu_solve(T, batch, 40, kernel="group", precision=precision)
+    rest = gpu_solve(T, batch, 60, init=dict(c=part["c"], lam=part["lam"]), kernel="group", precision=precision)
     for k in ("c", "lam", "resid"):
         assert np.array_equal(full[k], rest[k]), k
 

@@ -74,11 +74,12 @@ def test_mfma_group_size_does_not_change_results(T):
             assert np.array_equal(out[k], ref[k]), (group, k)
 
 
-def test_mfma_resume_equals_continuous_bitwise(T):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mfma_resume_equals_continuous_bitwise(T, precision):
     batch = S.workload_small(5)
-    full = gpu_solve(T, batch, 100, kernel="mfma")
-    part = gpu_solve(T, batch, 40, kernel="mfma")
-    rest = gpu_solve(T, batch, 60, init=dict(c=part["c"], lam=part["lam"]), kernel="mfma")
+    full = gpu_solve(T, batch, 100, kernel="mfma", precision=precision)
+    part = gpu_solve(T, batch, 40, kernel="mfma", precision=precision)
+    rest = gpu_solve(T, batch, 60, init=dict(c=part["c"], lam=part["lam"]), kernel="mfma", precision=precision)
     for k in ("c", "lam", "resid"):
         assert np.array_equal(full[k], rest[k]), k
 
