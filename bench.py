@@ -35,13 +35,13 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.65  # the same without packed FP32, which this li
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "2f833caa3f218bdb83bac50e2e2ef97100b62b2cb930ebe17a7120366f41cec8",
-              "bytes_per_launch": int((245.0 * 2.0 + 284.0) * 1024),
+              "sha256": "f7695494a702292395bbe247c4cb9aae49f70b2b4e28169963a0e4d513e32a7b",
+              "bytes_per_launch": int((245.5 * 2.0 + 284.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "c3c86e37bb36018d2be48210e2a045ca9b93a5e1e6a08cf1676bc0c88fa5a438",
-               "bytes_per_launch": int((77901.6 * 2.0 + 277296.6) * 1024),
+               "sha256": "3b5ce78f9dc58dd1277f63889e96f56893cadf6b05fa33bdd1e83768e070c63f",
+               "bytes_per_launch": int((87028.8 * 2.0 + 277380.4) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--warm-train", type=int, default=20000, help="dense: training scenes of the warm-start leg")
     ap.add_argument("--warm-test", type=int, default=2048, help="dense: held-out scenes of the warm-start leg")
     ap.add_argument("--warm-epochs", type=int, default=30, help="dense: training epochs of the warm-start leg")
-    ap.add_argument("--restart-at", type=int, default=30,
+    ap.add_argument("--restart-at", type=int, default=10,
                     help="warm start: restart the scenes still unconverged after this many iterations from the cold "
                          "start (within the same 300-iteration budget; 0 = never)")
     ap.add_argument("--train-scenes", type=int, default=100000, help="warmstart: solved scenes to train on")

@@ -35,7 +35,7 @@ DIMS = (64, 256, 3, 16896)
 # this many iterations start again from the cold start for the rest of the budget
 # (a warm start that converges does so in about 55 iterations; one that has not by
 # 30 is more often stalled than slow).
-RESTART_AT = 30
+RESTART_AT = 10
 GOALS = 256  # template goals per scene (4 lanes x 64 slots)
 ROW = 6 * T.N_COEF * GOALS
 

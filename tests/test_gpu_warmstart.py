@@ -5,7 +5,7 @@ kernels) on solutions of held-apart template scenes, then the solver runs to
 the stopping rule (best goal of each scene at max(r_obs, r_acc, r_nh) <= 1e-3,
 checked every 5 iterations, at most 300) on 4096 unseen scenes from the cold
 start (FP32) and from the network's prediction (split-BF16 solver; the cold start
-as fallback per goal after one iteration and per scene after 30). The warm
+as fallback per goal after one iteration and per scene after 10). The warm
 start must need fewer iterations on average at the same FP32 precision, take
 less wall-clock time per scene than the cold FP32 start, both over all scenes
 and over the scenes both bring to the tolerance, and bring at least as many
