@@ -64,7 +64,8 @@ typedef struct {
   float rho;      /* penalty weight rho_xy of eq. 10, also used for the heading block (eq. 13) */
   float a, b;     /* obstacle ellipse semi-axes incl. ego inflation (eq. 1e); > 0 */
   float v_min, v_max; /* velocity bounds (eq. 1d); 0 < v_min <= v_max (eq. 21 needs v_min > 0) */
-  float a_max;        /* acceleration bound (eq. 1d, eq. 5); > 0 */
+  float a_max;        /* acceleration bound (eq. 1d, eq. 5); >= 2^-63 (about 1.1e-19), so
+                         that a_max^2 is a normal FP32 number */
   float psi_max;      /* heading post-filter bound in radians (Sec. III, assumption 2) */
 } traj_params;
 

@@ -159,6 +159,8 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
       !finite_pos(p.a_max) || !finite_pos(p.psi_max))
     return fail(TRAJ_E_INVAL, "parameters must be finite and positive");
   if (p.v_min > p.v_max) return fail(TRAJ_E_INVAL, "v_min > v_max");
+  // the acceleration projection's reciprocal square root needs a_max^2 normal
+  if (p.a_max < 0x1p-63f) return fail(TRAJ_E_INVAL, "a_max must be at least 2^-63");
   if (n_shapes < 1 || n_shapes > 4096) return fail(TRAJ_E_INVAL, "n_shapes must be in [1, 4096]");
   Handle* h = new (std::nothrow) Handle();
   if (h == nullptr) return fail(TRAJ_E_NOMEM, "host allocation failed");
@@ -232,9 +234,10 @@ int traj_setup(const traj_params* params, const traj_shape* shapes, int n_shapes
 int traj_destroy(void* handle) {
   Handle* h = (Handle*)handle;
   if (h == nullptr) return TRAJ_OK;
-  if (h->d_shapes) hipFree(h->d_shapes);
-  if (h->d_tables) hipFree(h->d_tables);
-  if (h->d_tables64) hipFree(h->d_tables64);
+  // releasing is best effort: a failure leaves nothing the caller could act on
+  if (h->d_shapes) (void)hipFree(h->d_shapes);
+  if (h->d_tables) (void)hipFree(h->d_tables);
+  if (h->d_tables64) (void)hipFree(h->d_tables64);
   delete h;
   return TRAJ_OK;
 }

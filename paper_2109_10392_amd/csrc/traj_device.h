@@ -148,6 +148,23 @@ __device__ __forceinline__ int compact_candidates(bool hit, const float4& ob, fl
   return cnt;
 }
 
+// Obstacle polar variables at one sample inside a scaled ellipse (eqs. 15 and 22;
+// q = tx^2 + ty^2 < 1 in units scaled by (1/a, 1/b)): d/du - 1 = 1/du - 1 with
+// du = sqrt(q), added to s_o as (tx, ty) (1/du - 1), and the sample's squared
+// obstacle residual (a tx, b ty)^2 (1/du - 1)^2. On the obstacle centre alpha =
+// atan2(+0, +0) = 0 and d = 1. The hardware reciprocal square root equals the
+// library's for a normal argument but reads a denormal as 0, so an offset whose q
+// is below 2^-126 (under 1.1e-19 in scaled units, where the angle of eq. 22 is no
+// longer resolved) counts as the centre.
+__device__ __forceinline__ void obstacle_inside(float tx, float ty, float q, float a2, float b2, float& Sx,
+                                                float& Sy, float& ro) {
+  const bool centre = !(q >= 0x1p-126f);
+  const float f = __builtin_amdgcn_rsqf(q) - 1.f;
+  Sx = centre ? Sx + 1.f : fmaf(tx, f, Sx);
+  Sy = centre ? Sy : fmaf(ty, f, Sy);
+  ro = centre ? ro + a2 : fmaf(fmaf(a2 * tx, tx, b2 * ty * ty), f * f, ro);
+}
+
 // Minimum over each DPP row of 16 lanes, returned in every lane of the row.
 __device__ __forceinline__ float row_min(float v) {
   v = fminf(v, dpp<DPP_QUAD_1032>(v));
@@ -158,21 +175,20 @@ __device__ __forceinline__ float row_min(float v) {
 
 __device__ __forceinline__ float row_max(float v) { return -row_min(-v); }
 
-// sin and cos of |r| <= pi/2: Taylor series about 0 truncated after r^15 / r^16
-// (truncation error below 1e-11, so FP32 rounding dominates).
+// sin and cos of |r| <= pi/2: Taylor series about 0 truncated after r^13 / r^12
+// (alternating series: the truncation error is below the first omitted term,
+// 6.7e-10 for sin and 6.4e-9 for cos at pi/2, under FP32's rounding of values
+// near 1).
 __device__ __forceinline__ void sincos_taylor(float x, float* sn, float* cs) {
   const float x2 = x * x;
-  float ps = -7.6471637e-13f;                 // -1/15!
-  ps = fmaf(ps, x2, 1.6059044e-10f);          //  1/13!
+  float ps = 1.6059044e-10f;                  //  1/13!
   ps = fmaf(ps, x2, -2.5052108e-08f);         // -1/11!
   ps = fmaf(ps, x2, 2.7557319e-06f);          //  1/9!
   ps = fmaf(ps, x2, -1.9841270e-04f);         // -1/7!
   ps = fmaf(ps, x2, 8.3333333e-03f);          //  1/5!
   ps = fmaf(ps, x2, -1.6666667e-01f);         // -1/3!
   *sn = fmaf(ps * x2, x, x);
-  float pc = 4.7794773e-14f;                  //  1/16!
-  pc = fmaf(pc, x2, -1.1470746e-11f);         // -1/14!
-  pc = fmaf(pc, x2, 2.0876757e-09f);          //  1/12!
+  float pc = 2.0876757e-09f;                  //  1/12!
   pc = fmaf(pc, x2, -2.7557319e-07f);         // -1/10!
   pc = fmaf(pc, x2, 2.4801587e-05f);          //  1/8!
   pc = fmaf(pc, x2, -1.3888889e-03f);         // -1/6!

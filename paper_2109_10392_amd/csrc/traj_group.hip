@@ -231,7 +231,9 @@ __device__ __forceinline__ void accel_forms(const GConsts& K, const bool (&tv)[4
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
-    const float fa = (tv[r] && h2 > K.amax2) ? K.amax * rsqrtf(h2) - 1.f : 0.f;
+    // (a_max >= 2^-63, so h2 > a_max^2 is a normal number: the hardware reciprocal
+    // square root is the library's)
+    const float fa = (tv[r] && h2 > K.amax2) ? K.amax * __builtin_amdgcn_rsqf(h2) - 1.f : 0.f;
     sax[r] = xdd[r] * fa;
     say[r] = ydd[r] * fa;
     racc = fmaf(sax[r], sax[r], fmaf(say[r], say[r], racc));
@@ -245,7 +247,9 @@ __device__ __forceinline__ void velocity_forms(const GConsts& K, const bool (&tv
                                                float& r_psi) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
+    // (the hardware square root, within 1 ulp; the clamp to v_min > 0 absorbs a
+    // denormal argument read as 0)
+    const float v = fminf(fmaxf(__builtin_amdgcn_sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
     float sn, cs;
     sincos_heading(psi[r], &sn, &cs);
     ex[r] = tv[r] ? fmaf(v, cs, -xd[r]) : 0.f;
@@ -310,17 +314,7 @@ __device__ __forceinline__ void obstacle_forms(const GConsts& K, const float4* _
     if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (qq[r] < 1.f) {
-          if (qq[r] > 0.f) {
-            const float f = rsqrtf(qq[r]) - 1.f;
-            Sx[r] = fmaf(tx[r], f, Sx[r]);
-            Sy[r] = fmaf(ty[r], f, Sy[r]);
-            r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, r_obs);
-          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
-            Sx[r] += 1.f;
-            r_obs += K.a2;
-          }
-        }
+        if (qq[r] < 1.f) obstacle_inside(tx[r], ty[r], qq[r], K.a2, K.b2, Sx[r], Sy[r], r_obs);
       }
     }
   };

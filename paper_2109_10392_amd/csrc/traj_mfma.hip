@@ -127,13 +127,16 @@ __device__ __forceinline__ void samples(const Consts& K, const float2* __restric
     lylo = tv[r] ? min(lylo, ky) : lylo;
     lyhi = tv[r] ? max(lyhi, ky) : lyhi;
     // velocity (eq. 21), heading direction, z - x'
-    const float v = fminf(fmaxf(sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
+    // (the hardware square root, within 1 ulp; the clamp to v_min > 0 absorbs a
+    // denormal argument read as 0)
+    const float v = fminf(fmaxf(__builtin_amdgcn_sqrtf(fmaf(xd[r], xd[r], yd[r] * yd[r])), K.vmin), K.vmax);
     float sn, cs;
     sincos_heading(psi[r], &sn, &cs);
     const float ex = fmaf(v, cs, -xd[r]), ey = fmaf(v, sn, -yd[r]);
-    // acceleration polar variables (eq. 16)
+    // acceleration polar variables (eq. 16; a_max >= 2^-63, so h2 > a_max^2 is a
+    // normal number, where the hardware reciprocal square root is the library's)
     const float h2 = fmaf(xdd[r], xdd[r], ydd[r] * ydd[r]);
-    const float fa = h2 > K.amax2 ? K.amax * rsqrtf(h2) - 1.f : 0.f;
+    const float fa = h2 > K.amax2 ? K.amax * __builtin_amdgcn_rsqf(h2) - 1.f : 0.f;
     const float sax = xdd[r] * fa, say = ydd[r] * fa;
     const float ep = th[r] - psi[r];
     o.ex[r] = tv[r] ? ex : 0.f;
@@ -175,17 +178,7 @@ __device__ __forceinline__ void samples(const Consts& K, const float2* __restric
     if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (qq[r] < 1.f) {
-          if (qq[r] > 0.f) {
-            const float f = rsqrtf(qq[r]) - 1.f;
-            Sx[r] = fmaf(tx[r], f, Sx[r]);
-            Sy[r] = fmaf(ty[r], f, Sy[r]);
-            o.r_obs = fmaf(fmaf(K.a2 * tx[r], tx[r], K.b2 * ty[r] * ty[r]), f * f, o.r_obs);
-          } else {  // on the obstacle centre: alpha = atan2(+0, +0) = 0, d = 1
-            Sx[r] += 1.f;
-            o.r_obs += K.a2;
-          }
-        }
+        if (qq[r] < 1.f) obstacle_inside(tx[r], ty[r], qq[r], K.a2, K.b2, Sx[r], Sy[r], o.r_obs);
       }
     }
   }

@@ -175,14 +175,17 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     const float x = dotc(L.P[s], cx), y = dotc(L.P[s], cy);
     const float xdd = dotc(L.Pdd[s], cx), ydd = dotc(L.Pdd[s], cy);
     const float psi = dotc(L.P[s], cp);
-    // velocity, eq. 21
-    const float v = fminf(fmaxf(sqrtf(fmaf(xd[s], xd[s], yd[s] * yd[s])), G.vmin), G.vmax);
+    // velocity, eq. 21 (the hardware square root, within 1 ulp; a denormal argument
+    // reads as 0, a difference below 1.1e-19 that the clamp to v_min > 0 absorbs)
+    const float v = fminf(fmaxf(__builtin_amdgcn_sqrtf(fmaf(xd[s], xd[s], yd[s] * yd[s])), G.vmin), G.vmax);
     float sn, cs;
     sincos_heading(psi, &sn, &cs);
     const float ex = fmaf(v, cs, -xd[s]), ey = fmaf(v, sn, -yd[s]);  // z - x'
     // acceleration polar variables, eq. 16: d_a = min(a_max, h), s_a = (x'', y'') (d_a / h - 1)
     const float h2 = fmaf(xdd, xdd, ydd * ydd);
-    const float fa = h2 > G.amax2 ? G.amax * rsqrtf(h2) - 1.f : 0.f;
+    // (a_max >= 2^-63, so h2 > a_max^2 is a normal number: the hardware reciprocal
+    // square root is the library's)
+    const float fa = h2 > G.amax2 ? G.amax * __builtin_amdgcn_rsqf(h2) - 1.f : 0.f;
     const float sax = xdd * fa, say = ydd * fa;
     // obstacle polar variables, eqs. 15 and 22, in units scaled by (1/a, 1/b):
     // s_o = sum_j dx_j (d_j / du_j - 1), non-zero only inside an ellipse.
@@ -200,16 +203,20 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
     constexpr int TOP = 0x7fffffff, BOTTOM = (int)0x80000000;
     const int xlo = row_min_i(L.val[s] ? kx : TOP), xhi = row_max_i(L.val[s] ? kx : BOTTOM);
     const int ylo = row_min_i(L.val[s] ? ky : TOP), yhi = row_max_i(L.val[s] ? ky : BOTTOM);
-    // lane j tests obstacle j against each row's box, read from the row's first lane.
-    // The reads stay outside any lane-dependent branch (bitwise, not short-circuit,
-    // tests): a lane read while inactive would return a stale register.
+    // lane j tests obstacle j against each row's box: every lane stores its row's box
+    // behind the wave's candidate list (all lanes, so that the last DPP step of the
+    // row extremes stays fused), and every lane reads the four rows' first entries
+    // back (same address per read: a broadcast). The previous reads of these words
+    // fed the previous slot's candidate test, so they completed before these writes.
+    int4* rbox = reinterpret_cast<int4*>(clist + CLIST);
+    rbox[lane] = make_int4(xlo, xhi, ylo, yhi);
+    wave_sync_lds();
     bool hit = false;
 #pragma unroll
     for (int rw = 0; rw < WAVE / 16; ++rw) {
-      const int rxl = rdlane_i(xlo, 16 * rw), rxh = rdlane_i(xhi, 16 * rw);
-      const int ryl = rdlane_i(ylo, 16 * rw), ryh = rdlane_i(yhi, 16 * rw);
+      const int4 rb = rbox[16 * rw];
       const int4 bx = L.box[s][rw];
-      hit = hit | ((rxh > bx.x) & (rxl < bx.y) & (ryh > bx.z) & (ryl < bx.w));
+      hit = hit | ((rb.y > bx.x) & (rb.x < bx.y) & (rb.w > bx.z) & (rb.z < bx.w));
     }
     // the candidates' scaled states, compacted in index order into the wave's list
     const int cnt = compact_candidates(hit && lane < G.m, L.ob, clist);
@@ -226,16 +233,7 @@ __device__ __forceinline__ void projections(const Goal& G, const Lane<S>& L, con
       if (fminf(fminf(qq[0], qq[1]), fminf(qq[2], qq[3])) < 1.f) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (qq[u] < 1.f) {
-            // inside: d/du - 1 = 1/du - 1 with du = sqrt(q) (q is a normal number or 0
-            // here, where the hardware reciprocal square root is the library's); on the
-            // obstacle centre alpha = atan2(+0, +0) = 0 and d = 1
-            const bool centre = !(qq[u] > 0.f);
-            const float f = __builtin_amdgcn_rsqf(qq[u]) - 1.f;
-            Sx = centre ? Sx + 1.f : fmaf(tx[u], f, Sx);
-            Sy = centre ? Sy : fmaf(ty[u], f, Sy);
-            ro = centre ? ro + G.a2 : fmaf(fmaf(G.a2 * tx[u], tx[u], G.b2 * ty[u] * ty[u]), f * f, ro);
-          }
+          if (qq[u] < 1.f) obstacle_inside(tx[u], ty[u], qq[u], G.a2, G.b2, Sx, Sy, ro);
         }
       }
     };
@@ -549,7 +547,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_am(SolveArgs A) {
                                                           // x range, y range (scaled, inflated)
   __shared__ float ex[2 * 2 * WAVE];                // partial sums of a goal's two waves (double-buffered)
   __shared__ float4 slots4[GPW * WPG][SLOT_FLOATS / 4];  // each wave's broadcast slots
-  __shared__ float4 clists[GPW * WPG][CLIST];           // each wave's obstacle candidates
+  __shared__ float4 clists[GPW * WPG][CLIST + WAVE];  // each wave's obstacle candidates, then its
+                                                       // lanes' row boxes of the current slot
   __shared__ int sh[2];
   __shared__ int scan[GOALS_PER_WG];
   locate(A.goal_off, A.n_scenes, GPW, sh, scan, xcd_block((int)blockIdx.x, (int)gridDim.x));

@@ -44,7 +44,7 @@ def _params(**over):
 
 
 @pytest.mark.parametrize("bad", [dict(n_coef=10), dict(rho=0.0), dict(a=-1.0), dict(v_min=0.0),
-                                 dict(v_min=40.0), dict(a_max=float("nan"))])
+                                 dict(v_min=40.0), dict(a_max=float("nan")), dict(a_max=1e-20)])
 def test_setup_rejects_bad_parameters_before_any_device_work(bad):
     L = T.lib()
     shp = (T.Shape * 1)(T.Shape(100, 10.0, 10))
