@@ -35,13 +35,13 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.65  # the same without packed FP32, which this li
 MEASURED_TRAFFIC = {
     "dense": {"sources": ("paper_2109_10392_amd/csrc/traj_solve.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                           "paper_2109_10392_amd/csrc/traj_device.h"),
-              "sha256": "f7695494a702292395bbe247c4cb9aae49f70b2b4e28169963a0e4d513e32a7b",
-              "bytes_per_launch": int((245.5 * 2.0 + 284.0) * 1024),
+              "sha256": "4193d025e3eed1e9ea8ab120a2ce1e179ab1460202e762810672a87d4e0b88d8",
+              "bytes_per_launch": int((242.5 * 2.0 + 284.0) * 1024),
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "3b5ce78f9dc58dd1277f63889e96f56893cadf6b05fa33bdd1e83768e070c63f",
-               "bytes_per_launch": int((87028.8 * 2.0 + 277380.4) * 1024),
+               "sha256": "6728c56c51a9deac05e9521f52535531fb67faaa690f3ca5f3e876c3952c92ac",
+               "bytes_per_launch": int((71145.4 * 2.0 + 277471.9) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 
