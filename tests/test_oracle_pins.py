@@ -625,3 +625,83 @@ def test_multiplier_components_along_the_boundary_rows_change_no_iterate():
         ref = getattr(a, name)
         assert np.max(np.abs(getattr(b, name) - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))
     assert max(np.max(np.abs(getattr(c, n) - getattr(a, n))) for n in ("c_x", "c_y", "c_psi")) > 1e-3
+
+
+def _velocity_rows(prob, sc, st):
+    """(gap, row^2 / (2 v) with its sign, speed) per sample and goal: the R8 gap
+    x' cos psi + y' sin psi - ||(x', y')|| and the velocity rows of F c - g (eq. 8c)."""
+    xi_x, xi_y = O.obstacle_predictions(sc.obs, prob.t)
+    g = O._g(prob, st, xi_x, xi_y)
+    m, n = prob.m, prob.n
+    r = prob.F @ np.concatenate([st.c_x, st.c_y], axis=0) - g
+    L = (m + 2) * n
+    ex, ey = r[(m + 1) * n:L], r[L + (m + 1) * n:]
+    xd, yd = prob.Pd @ st.c_x, prob.Pd @ st.c_y
+    psi = prob.P @ st.c_psi
+    speed = np.hypot(xd, yd)
+    gap = xd * np.cos(psi) + yd * np.sin(psi) - speed
+    return gap, -(ex ** 2 + ey ** 2) / (2.0 * speed), speed
+
+
+def _check_velocity_rows(prob, sc, st):
+    gap, want, speed = _velocity_rows(prob, sc, st)
+    inside = (speed > prob.v_min) & (speed < prob.v_max)
+    assert inside.mean() > 0.9
+    assert np.all(gap <= 1e-12)                     # Cauchy-Schwarz
+    np.testing.assert_allclose(gap[inside], want[inside], rtol=1e-7, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_velocity_rows_follow_eq21_and_the_r8_gap(seed):
+    """Eq. 21 as printed (reading R8: v = ||(x', y')||, not the minimiser
+    x' cos psi + y' sin psi of eq. 14 at a fixed heading). Where the speed lies
+    inside (v_min, v_max) the velocity rows of F c - g are
+    (x', y') - v (cos psi, sin psi) with v = ||(x', y')||, so the R8 gap equals
+    -|row|^2 / (2 v) exactly: both are -v (1 - cos(theta - psi)). The gap is thus
+    second order in the non-holonomic residual; its 2-norm over the samples of the
+    meta-cost-best goal is printed beside r_nh as the diagnostic. Checked after 3
+    iterations, where theta - psi is still large enough that the literal
+    minimiser (which gives -v sin^2(theta - psi) / 2) differs beyond the
+    tolerance, and after 100."""
+    from threadpoolctl import threadpool_limits
+    sc = S.workload_small(seed).scenes[0]
+    prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+    with threadpool_limits(1):
+        for iters in (3, 100):
+            st = O.solve(prob, sc.ego, sc.obs, sc.goals, iters)
+            _check_velocity_rows(prob, sc, st)
+        best = O.best_goal(O.meta_cost(prob, st.c_x, st.c_y, st.c_psi, v_ref=float(sc.ego[2])))
+        gap = _velocity_rows(prob, sc, st)[0][:, best]
+        print(f"seed {seed}: best goal {best}, R8 gap {np.linalg.norm(gap):.2e}, r_nh {st.resid[2, best]:.2e}")
+
+
+def _literal_minimiser_oracle():
+    """The oracle with eq. 21 replaced by the minimiser of eq. 14 at the sweep's
+    heading, v = clip(x' cos psi + y' sin psi)."""
+    ns = _planted_oracle("    st.v = project_velocity(prob, xd, yd)\n",
+                         "    st.v = project_velocity(prob, xd, yd, P @ st.c_psi)\n")
+    ns["project_velocity"] = lambda prob, xd, yd, psi: np.clip(xd * np.cos(psi) + yd * np.sin(psi),
+                                                               prob.v_min, prob.v_max)
+    return ns
+
+
+@pytest.mark.parametrize("mistake", ["literal minimiser", "theta for psi"])
+def test_velocity_rows_pin_rejects_planted_mistakes(mistake):
+    """The literal minimiser of eq. 14 at a fixed heading in place of eq. 21, or
+    the direction of motion theta in place of the heading psi in g, fails the
+    identity of test_velocity_rows_follow_eq21_and_the_r8_gap on every seed."""
+    from threadpoolctl import threadpool_limits
+    if mistake == "literal minimiser":
+        ns = _literal_minimiser_oracle()
+    else:
+        ns = _planted_oracle("st.psi = P @ st.c_psi", "st.psi = st.theta")
+    failed = 0
+    with threadpool_limits(1):
+        for seed in range(4):
+            sc = S.workload_small(seed).scenes[0]
+            prob = ns["Problem"](sc.n_time, sc.t_f, sc.obs.shape[0], PARAMS)
+            st = ns["solve"](prob, sc.ego, sc.obs, sc.goals, 3)
+            gap, want, speed = _velocity_rows(prob, sc, st)
+            inside = (speed > prob.v_min) & (speed < prob.v_max)
+            failed += not np.allclose(gap[inside], want[inside], rtol=1e-7, atol=1e-13)
+    assert failed == 4
