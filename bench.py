@@ -217,6 +217,43 @@ def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, 
             "single_tile_equals": single_equal}
 
 
+def residual_curve(seeds=range(100), chunk=5, total=300, tol=1e-3):
+    """Residuals over the iterations (the quantity of Fig. 3a) at the paper's scene
+    scale, batched: the 11-goal scenes of `seeds` (10 obstacles, 4 lanes, T = 100)
+    in one batch, a cold FP32 solve resumed chunk by chunk (bitwise the continuous
+    solve) and scored after every chunk. Per chunk: the median over the scenes of
+    max(r_obs, r_acc, r_nh) of each scene's meta-cost-best goal (eq. 25), and the
+    share of scenes where it is at or below `tol`. Runs after the timed region."""
+    import numpy as np
+    import torch
+    from paper_2109_10392_amd import scenes as S
+    from paper_2109_10392_amd import traj as T
+    batch = S.Batch([S.workload_small(s).scenes[0] for s in seeds])
+    solver = T.Solver(S.DEFAULT_PARAMS, batch.shapes())
+    solver.set_tile("wave", 16, True, 2)
+    db = T.DeviceBatch.from_batch(batch)
+    st = T.DeviceState.empty(batch.n_goals)
+    v_ref = torch.tensor([float(s.ego[2]) for s in batch.scenes], device="cuda")
+    cost = torch.zeros(batch.n_goals, device="cuda")
+    best = torch.zeros(batch.n_scenes, device="cuda", dtype=torch.int32)
+    first = torch.as_tensor(np.asarray(batch.goal_off()[:-1], np.int64), device="cuda")
+    med, share = [], []
+    for k in range(total // chunk):
+        solver.solve(db, st, chunk, from_state=k > 0)
+        solver.score(db, st, v_ref, cost, best)
+        r = st.resid[:3].amax(0)
+        rb = torch.where(best >= 0, r[first + best.clamp(min=0).long()], torch.full_like(r[:1], float("inf")))
+        med.append(rb.median())
+        share.append((rb <= tol).float().mean())
+    torch.cuda.synchronize()
+    solver.close()
+    return {"scenes": f"the 11-goal scenes of seeds {seeds[0]}-{seeds[-1]} in one batch ({batch.n_scenes} scenes, "
+                      f"{batch.n_goals} goals), cold start, FP32",
+            "iterations": list(range(chunk, total + 1, chunk)),
+            "best_goal_max_residual_median": [float(f"{x:.3g}") for x in torch.stack(med).tolist()],
+            "share_at_or_below_1e-3": [round(x, 3) for x in torch.stack(share).tolist()]}
+
+
 def run_warmstart(args):
     """Learned warm start: train on solved template scenes, then time cold FP32 and
     warm + split-BF16 solves of held-out scenes to residual 1e-3 (ms per scene)."""
@@ -327,7 +364,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="uneven: skip the graph-replay and separate-launch comparisons (profiling)")
+                    help="skip the runs after the timed region (profiling): dense: the residual curve; "
+                         "uneven: the graph-replay and separate-launch comparisons")
     ap.add_argument("--cpu-goals", type=int, default=320,
                     help="goals of the one-core CPU oracle sample (about 8 s; the all-core leg solves all 1024)")
     ap.add_argument("--kernel", choices=["auto", "wave", "mfma", "group"], default="auto",
@@ -486,6 +524,8 @@ def main():
                      "target_frac": 0.5},
         "best_goal": int(best[0].item()),
     }
+    if args.workload == "dense" and not args.no_extras:
+        out["residual_curve"] = residual_curve()
     if args.workload == "uneven" and not args.no_extras:
         out["uneven"] = uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent,
                                       total_ms / args.steps, waves)
