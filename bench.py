@@ -40,8 +40,8 @@ MEASURED_TRAFFIC = {
               "profile": "profiles/k_am_wave2_dense1024.md"},
     "uneven": {"sources": ("paper_2109_10392_amd/csrc/traj_group.hip", "paper_2109_10392_amd/csrc/traj_internal.h",
                            "paper_2109_10392_amd/csrc/traj_device.h", "paper_2109_10392_amd/csrc/traj_mma.h"),
-               "sha256": "6728c56c51a9deac05e9521f52535531fb67faaa690f3ca5f3e876c3952c92ac",
-               "bytes_per_launch": int((71145.4 * 2.0 + 277471.9) * 1024),
+               "sha256": "7d1f120b983d3441d256ca93687cd90bde63e82e8b929b6aa8b81407ef833698",
+               "bytes_per_launch": int((87925.4 * 2.0 + 277450.9) * 1024),
                "profile": "profiles/k_am_group_uneven512.md"},
 }
 

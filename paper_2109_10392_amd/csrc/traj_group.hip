@@ -494,7 +494,6 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
     }
     return v;
   };
-  // heading input: W = P^T theta, theta = atan2(y', x') at every sample
   // heading input: W = P^T theta, theta = atan2(y', x') at every sample; theta is
   // kept in this wave's LDS slice for the projection sweep that follows
   auto heading_sweep = [&]() -> f4 {
@@ -509,18 +508,15 @@ __device__ void solve_group(const SolveArgs& A, const int32_t* __restrict__ perm
         nd = pk[((w + 1) * PACK_SLOTS + 1) * WAVE + lane];
         np = pk[((w + 1) * PACK_SLOTS + 3) * WAVE + lane];
       }
-      // the heading input is contracted in FP32 in both forms (it feeds the heading
-      // operator, whose products cancel)
-      Operand<MODE> evd;
-      Operand<TRAJ_MODE_FP32> ctp;
+      Operand<MODE> evd, ctp;
       to_operand<MODE>(evd, vd);
-      to_operand<TRAJ_MODE_FP32>(ctp, vp);
+      to_operand<MODE>(ctp, vp);
       const f4 xd = plus_slope(eval<MODE>(evd, cx, cxb), Lx), yd = plus_slope(eval<MODE>(evd, cy, cyb), Ly);
       f4 th;
 #pragma unroll
       for (int r = 0; r < 4; ++r) th[r] = (gv && TILE * w + 4 * q + r < n) ? atan2_heading(yd[r], xd[r]) : 0.f;
       sth[w * WAVE + lane] = f4to(th);
-      W = contract<TRAJ_MODE_FP32>(ctp, th, W);
+      W = contract<MODE>(ctp, th, W);
     }
     return W;
   };

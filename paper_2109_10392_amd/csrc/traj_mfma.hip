@@ -41,7 +41,6 @@ template <int MODE>
 struct Ops {
   Operand<MODE> ev[3];  // P, P', P'' [t = 16w + j][4q + kk]
   Operand<MODE> ct[3];  // P, P', P'' [16w + 4q + r][j]
-  float ctp[4];         // split-BF16 form: P [16w + 4q + r][j] in FP32 for the heading input
   PsiOps psi;           // the x/y operators (FP64) are read from the tables at each use
 };
 
@@ -91,10 +90,6 @@ __device__ void load_ops(Ops<MODE>& O, const float* __restrict__ T, const double
     }
     make_operand<MODE>(O.ev[mi], ev);
     make_operand<MODE>(O.ct[mi], ct);
-    if (MODE == TRAJ_MODE_BF16X3 && mi == 0) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) O.ctp[kk] = ct[kk];
-    }
   }
   load_psi_ops(O.psi, T, n, j, q);
 }
@@ -394,16 +389,7 @@ __global__ __launch_bounds__(768) void k_am_mfma(SolveArgs A, int G) {
       const bool tv = gv && (TILE * w + 4 * q + r) < n;
       th[r] = tv ? atan2_heading(yd[r], xd[r]) : 0.f;
     }
-    // the heading input is contracted in FP32 in both forms (it feeds the heading
-    // operator, whose products cancel)
-    if constexpr (MODE == TRAJ_MODE_FP32) {
-      W_ = contractO<MODE>(O, 0, th, zero);
-    } else {
-      Operand<TRAJ_MODE_FP32> ctp;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) ctp.v[kk] = O.ctp[kk];
-      W_ = contract<TRAJ_MODE_FP32>(ctp, th, zero);
-    }
+    W_ = contractO<MODE>(O, 0, th, zero);
     E_ = contractO<MODE>(O, 0, ep, zero);
     exchange(ex, buf, Wl, w, lane, W_, E_);
     buf ^= 1;
