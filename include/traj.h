@@ -47,8 +47,9 @@ extern "C" {
                                      reset; scenes already done are left untouched and the
                                      others start as the other flags say                      */
 #define TRAJ_PREC_FP32 0x0u       /* FP32 arithmetic, x/y step operators in FP64 (default)   */
-#define TRAJ_PREC_BF16X3 0x10u    /* matrix-core kernel, every contraction and apply in split
-                                     BF16 (hi + lo, three products) with FP32 accumulation   */
+#define TRAJ_PREC_BF16X3 0x10u    /* matrix-core kernel: every contraction in split BF16 (hi
+                                     + lo, three products), every inverse x right-hand side
+                                     in a three-part split (six products), FP32 accumulation */
 #define TRAJ_KERNEL_AUTO 0x0u     /* kernel from the handle's tile setting (traj_set_tile)   */
 #define TRAJ_KERNEL_WAVE 0x100u   /* one wavefront per goal, lanes over time                 */
 #define TRAJ_KERNEL_MFMA 0x200u   /* matrix-core kernel: goal groups x 16-sample time tiles  */
