@@ -76,18 +76,24 @@ def algorithmic_flops_per_goal_iter(n, m, N=N_COEF):
 
 def _oracle_chunk(args):
     """One worker of the CPU baseline: the FP64 oracle on goals [lo, hi) of the
-    dense scene of `seed`, one BLAS thread; returns the seconds of the solve."""
-    seed, lo, hi, iters = args
+    dense scene of `seed`, one BLAS thread, with every goal's final lateral
+    position moved by `shift` metres; returns the seconds of the solve and the
+    coefficients [3][11][hi - lo]."""
+    seed, lo, hi, iters = args[:4]
+    shift = args[4] if len(args) > 4 else 0.0
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import traj_oracle as O
     from paper_2109_10392_amd import scenes as S
     sc = S.workload_dense(seed).scenes[0]
+    goals = sc.goals[lo:hi].astype(np.float64)
+    goals[:, 1] += shift
     with threadpool_limits(1):
         prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], S.DEFAULT_PARAMS)
         t0 = time.perf_counter()
-        O.solve(prob, sc.ego, sc.obs, sc.goals[lo:hi], iters)
-        return time.perf_counter() - t0
+        st = O.solve(prob, sc.ego, sc.obs, goals, iters)
+        return time.perf_counter() - t0, np.stack([st.c_x, st.c_y, st.c_psi])
 
 
 def cpu_model():
@@ -112,13 +118,26 @@ def cpu_baseline(seed, iters, one_core_goals, max_workers=16):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     workers = max(1, min(cores, max_workers))
     n_goals = 1024
-    dt1 = _oracle_chunk((seed, 0, one_core_goals, iters))
+    dt1 = _oracle_chunk((seed, 0, one_core_goals, iters))[0]
     chunks = [(seed, n_goals * w // workers, n_goals * (w + 1) // workers, iters) for w in range(workers)]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         list(ex.map(_oracle_chunk, [(seed, 0, 1, 1)] * workers))  # start every worker and import first
         t0 = time.perf_counter()
-        list(ex.map(_oracle_chunk, chunks))
+        parts = list(ex.map(_oracle_chunk, chunks))
         dtn = time.perf_counter() - t0
+        # the same goals moved by 1e-6 m (below FP32's resolution of the inputs): where
+        # that moves the FP64 result by more than 2e-6 the goal sits at a bifurcation
+        shifted = list(ex.map(_oracle_chunk, [ch + (1e-6,) for ch in chunks]))
+    import numpy as np
+
+    from oracle import traj_oracle as O
+    from paper_2109_10392_amd import scenes as S
+    c = np.concatenate([p[1] for p in parts], axis=2)
+    c_shift = np.concatenate([p[1] for p in shifted], axis=2)
+    bifurcating = _rel_coef_err(c_shift, c) > 2e-6
+    sc = S.workload_dense(seed).scenes[0]
+    prob = O.Problem(sc.n_time, sc.t_f, sc.obs.shape[0], S.DEFAULT_PARAMS)
+    best = O.best_goal(O.meta_cost(prob, c[0], c[1], c[2], v_ref=float(sc.ego[2])))
     model = cpu_model()
     return {"value": n_goals * iters / dtn, "unit": "goal-trajectories*iters/s", "cores": workers, "kind": "oracle",
             "sample": f"all {n_goals} goals of the dense scene (seed {seed}), {iters} iterations, FP64 NumPy/SciPy "
@@ -127,7 +146,34 @@ def cpu_baseline(seed, iters, one_core_goals, max_workers=16):
             "cpu_model": model, "host_cores": cores,
             "single_core": {"value": one_core_goals * iters / dt1, "cores": 1,
                             "sample": f"{one_core_goals} of the 1024 goals, {iters} iterations, 1 BLAS thread, "
-                                      f"{dt1:.1f} s"}}
+                                      f"{dt1:.1f} s"},
+            "_oracle_c": c, "_oracle_best": best, "_bifurcating": bifurcating}
+
+
+def _rel_coef_err(c, c_ref):
+    """Per goal, the largest relative coefficient difference over the three axes:
+    max |c - c_ref| / max(max |c_ref|, 1) per axis ([3][11][B] arrays)."""
+    import numpy as np
+    num = np.abs(np.asarray(c, np.float64) - c_ref).max(axis=1)
+    den = np.maximum(np.abs(c_ref).max(axis=1), 1.0)
+    return (num / den).max(axis=0)
+
+
+def parity_vs_oracle(c_gpu, c_ref, bifurcating, best_gpu, best_ref):
+    """The timed solve's result against the oracle's on the same scene and
+    iteration count: the distribution over the goals of _rel_coef_err, over all
+    goals and over those whose FP64 result is determined (not moved past 2e-6 by a
+    1e-6 m goal shift; at a bifurcation FP32 and FP64 may take different
+    branches, each correct), and both best goals."""
+    import numpy as np
+    err = _rel_coef_err(c_gpu, c_ref)
+    det = err[~bifurcating]
+    q = lambda e, p: float(f"{np.percentile(e, p):.3g}") if e.size else None
+    return {"goals": int(err.size), "rel_coef_err_median": q(err, 50), "p90": q(err, 90), "max": q(err, 100),
+            "within_1e-4": int(np.count_nonzero(err <= 1e-4)),
+            "determined_goals": int(det.size), "determined_max": q(det, 100),
+            "determined_within_1e-4": int(np.count_nonzero(det <= 1e-4)),
+            "best_goal_gpu": int(best_gpu), "best_goal_oracle": int(best_ref)}
 
 
 def uneven_extras(T, S, solver, batch, db, st, v_ref, cost, best, args, kernel, group, persistent, one_launch_ms,
@@ -598,6 +644,10 @@ def main():
                      "target_frac": 0.5},
         "best_goal": int(best[0].item()),
     }
+    if cpu is not None:
+        ref_c, ref_best, bif = cpu.pop("_oracle_c"), cpu.pop("_oracle_best"), cpu.pop("_bifurcating")
+        if args.workload == "dense" and args.obstacle_range == 80.0 and args.precision == "fp32":
+            cpu["parity"] = parity_vs_oracle(st.c.cpu().numpy(), ref_c, bif, best[0].item(), ref_best)
     if args.workload == "dense" and not args.no_extras:
         out["residual_curve"] = residual_curve()
     if args.workload == "uneven" and not args.no_extras:
