@@ -31,6 +31,7 @@ __device__ int scene_of(const int32_t* goal_off, int n_scenes, int g) {
 constexpr int COST_LANES = 16;
 constexpr int COST_THREADS = 256;
 constexpr int COST_GOALS = COST_THREADS / COST_LANES;
+static_assert(COST_LANES == TILE_T, "a goal's lanes walk the packed tiles' sample rows");
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_row(float v) {
@@ -86,20 +87,28 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
   }
   const float dt = sd.t_f / (float)(n - 1);
   const float ia = 1.f / A.a, ib = 1.f / A.b;
-  const float* P0 = T + tab_basis(n, 0);
-  const float* P1 = T + tab_basis(n, 1);
+  // the basis rows of sample t = 16 w + r from the packed tiles: P[t][4q .. 4q + 3]
+  // at lane 16 q + r of tile w's slot 0, P' in slot 1 (zero past column NC), so a
+  // sample takes six 16-byte reads from one address instead of 22 strided ones
+  const float4* pk = reinterpret_cast<const float4*>(T + tab_pack(n));
   float acc = 0.f, pmax = 0.f, clear = __builtin_inff();
-  for (int t = r; t < n; t += COST_LANES) {
+  for (int t = r, w = 0; t < n; t += COST_LANES, ++w) {
+    const float4* row = pk + w * PACK_SLOTS * WAVE + r;
+    float p[4 * 3], pd[4 * 3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float4 a = row[16 * q], b = row[WAVE + 16 * q];
+      p[4 * q] = a.x; p[4 * q + 1] = a.y; p[4 * q + 2] = a.z; p[4 * q + 3] = a.w;
+      pd[4 * q] = b.x; pd[4 * q + 1] = b.y; pd[4 * q + 2] = b.z; pd[4 * q + 3] = b.w;
+    }
     float xd = 0.f, yd = 0.f, x = 0.f, y = 0.f, psi = 0.f;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const float p = P0[k * n + t];
-      const float pd = P1[k * n + t];
-      xd = fmaf(pd, cx[k], xd);
-      yd = fmaf(pd, cy[k], yd);
-      x = fmaf(p, cx[k], x);
-      y = fmaf(p, cy[k], y);
-      psi = fmaf(p, cp[k], psi);
+      xd = fmaf(pd[k], cx[k], xd);
+      yd = fmaf(pd[k], cy[k], yd);
+      x = fmaf(p[k], cx[k], x);
+      y = fmaf(p[k], cy[k], y);
+      psi = fmaf(p[k], cp[k], psi);
     }
     // squared scaled distance to every obstacle's constant-velocity prediction (eq. 1e)
     const float tm = (float)t * dt;
