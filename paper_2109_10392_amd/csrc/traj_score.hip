@@ -56,9 +56,40 @@ __device__ __forceinline__ float row_max(float v) {
   return fmaxf(v, dpp_row<DPP_MIRROR>(v));
 }
 
+// Obstacle predictions staged in LDS by a workgroup whose goals all belong to
+// one scene (at most this many (obstacle, sample) pairs).
+constexpr int PRED_MAX = 2048;
+
 __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
   const int r = threadIdx.x & (COST_LANES - 1);
   const int g = blockIdx.x * COST_GOALS + (int)(threadIdx.x / COST_LANES);
+  // The collision post-check's predictions x_j + v_j t of each (obstacle, sample)
+  // pair are the same for every goal of a scene: a workgroup whose goals share
+  // one scene forms them once in LDS (the same fused multiply-adds, so the same
+  // values). Decided per workgroup, before any thread leaves.
+  __shared__ float2 spred[PRED_MAX];
+  bool staged = false;
+  if (A.clear_min > 0.f && A.n_goals > 0) {
+    const int ga = blockIdx.x * COST_GOALS, gz = min(ga + COST_GOALS, A.n_goals) - 1;
+    const int sa = scene_of(A.goal_off, A.n_scenes, ga);
+    const int id = A.shape_id[sa];
+    if (sa == scene_of(A.goal_off, A.n_scenes, gz) && id >= 0 && id < A.n_shapes &&
+        !(A.skip != nullptr && A.skip[sa] != 0)) {
+      const ShapeDesc sd = A.shapes[id];
+      const int o0 = A.obs_off[sa], m = A.obs_off[sa + 1] - o0;
+      if (obstacles_ok(o0, m, sd.m) && m * sd.n <= PRED_MAX) {
+        const float dt = sd.t_f / (float)(sd.n - 1);
+        for (int e = threadIdx.x; e < m * sd.n; e += COST_THREADS) {
+          const int j = e / sd.n, t = e - j * sd.n;
+          const float4 o = reinterpret_cast<const float4*>(A.obs)[o0 + j];
+          const float tm = (float)t * dt;
+          spred[e] = make_float2(fmaf(o.z, tm, o.x), fmaf(o.w, tm, o.y));
+        }
+        staged = true;
+      }
+    }
+  }
+  __syncthreads();
   if (g >= A.n_goals) return;  // whole rows leave together
   const int s = scene_of(A.goal_off, A.n_scenes, g);
   if (A.skip != nullptr && A.skip[s] != 0) return;
@@ -111,11 +142,19 @@ __global__ __launch_bounds__(COST_THREADS) void k_cost(ScoreArgs A) {
       psi = fmaf(p[k], cp[k], psi);
     }
     // squared scaled distance to every obstacle's constant-velocity prediction (eq. 1e)
-    const float tm = (float)t * dt;
-    for (int j = 0; j < m; ++j) {
-      const float4 o = reinterpret_cast<const float4*>(A.obs)[o0 + j];
-      const float dx = (x - fmaf(o.z, tm, o.x)) * ia, dy = (y - fmaf(o.w, tm, o.y)) * ib;
-      clear = fminf(clear, fmaf(dx, dx, dy * dy));
+    if (staged) {
+      for (int j = 0; j < m; ++j) {
+        const float2 pr = spred[j * n + t];
+        const float dx = (x - pr.x) * ia, dy = (y - pr.y) * ib;
+        clear = fminf(clear, fmaf(dx, dx, dy * dy));
+      }
+    } else {
+      const float tm = (float)t * dt;
+      for (int j = 0; j < m; ++j) {
+        const float4 o = reinterpret_cast<const float4*>(A.obs)[o0 + j];
+        const float dx = (x - fmaf(o.z, tm, o.x)) * ia, dy = (y - fmaf(o.w, tm, o.y)) * ib;
+        clear = fminf(clear, fmaf(dx, dx, dy * dy));
+      }
     }
     const float v = sqrtf(fmaf(xd, xd, yd * yd));
     const float dv = v - vref;
