@@ -20,3 +20,24 @@ def test_more_than_one_gpu_exits_with_a_message():
     import sys
     out = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert out.returncode != 0 and "one GPU" in out.stdout + out.stderr
+
+
+def test_parity_statement_splits_determined_goals():
+    """parity_vs_oracle: per-goal relative coefficient error on the measure of the
+    parity tests (max over axes of max |dc| / max(max |c_ref|, 1)), reported over
+    all goals and over the determined ones."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+    c_ref = rng.normal(0.0, 5.0, (3, 11, 6))
+    c = c_ref.copy()
+    c[1, 3, 0] += 1e-5 * max(np.abs(c_ref[1, :, 0]).max(), 1.0)   # goal 0: 1e-5
+    c[2, 7, 1] += 0.5 * max(np.abs(c_ref[2, :, 1]).max(), 1.0)    # goal 1: 0.5, at a bifurcation
+    c[0, 0, 2] += 3e-4 * max(np.abs(c_ref[0, :, 2]).max(), 1.0)   # goal 2: 3e-4, determined
+    bif = np.array([False, True, False, False, False, False])
+    err = bench._rel_coef_err(c, c_ref)
+    assert np.allclose(err, [1e-5, 0.5, 3e-4, 0, 0, 0], rtol=1e-9, atol=1e-15)
+    out = bench.parity_vs_oracle(c, c_ref, bif, 4, 4)
+    assert out["goals"] == 6 and out["within_1e-4"] == 4
+    assert out["determined_goals"] == 5 and out["determined_within_1e-4"] == 4
+    assert abs(out["determined_max"] - 3e-4) < 1e-9 and abs(out["max"] - 0.5) < 1e-9
+    assert out["best_goal_gpu"] == out["best_goal_oracle"] == 4
