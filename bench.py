@@ -170,9 +170,10 @@ def parity_vs_oracle(c_gpu, c_ref, bifurcating, best_gpu, best_ref):
     det = err[~bifurcating]
     q = lambda e, p: float(f"{np.percentile(e, p):.3g}") if e.size else None
     return {"goals": int(err.size), "rel_coef_err_median": q(err, 50), "p90": q(err, 90), "max": q(err, 100),
-            "within_1e-4": int(np.count_nonzero(err <= 1e-4)),
+            "within_1e-4": int(np.count_nonzero(err <= 1e-4)), "within_1e-3": int(np.count_nonzero(err <= 1e-3)),
             "determined_goals": int(det.size), "determined_max": q(det, 100),
             "determined_within_1e-4": int(np.count_nonzero(det <= 1e-4)),
+            "determined_within_1e-3": int(np.count_nonzero(det <= 1e-3)),
             "best_goal_gpu": int(best_gpu), "best_goal_oracle": int(best_ref)}
 
 
@@ -646,7 +647,7 @@ def main():
     }
     if cpu is not None:
         ref_c, ref_best, bif = cpu.pop("_oracle_c"), cpu.pop("_oracle_best"), cpu.pop("_bifurcating")
-        if args.workload == "dense" and args.obstacle_range == 80.0 and args.precision == "fp32":
+        if args.workload == "dense" and args.obstacle_range == 80.0:
             cpu["parity"] = parity_vs_oracle(st.c.cpu().numpy(), ref_c, bif, best[0].item(), ref_best)
     if args.workload == "dense" and not args.no_extras:
         out["residual_curve"] = residual_curve()

@@ -37,7 +37,8 @@ def test_parity_statement_splits_determined_goals():
     err = bench._rel_coef_err(c, c_ref)
     assert np.allclose(err, [1e-5, 0.5, 3e-4, 0, 0, 0], rtol=1e-9, atol=1e-15)
     out = bench.parity_vs_oracle(c, c_ref, bif, 4, 4)
-    assert out["goals"] == 6 and out["within_1e-4"] == 4
+    assert out["goals"] == 6 and out["within_1e-4"] == 4 and out["within_1e-3"] == 5
     assert out["determined_goals"] == 5 and out["determined_within_1e-4"] == 4
+    assert out["determined_within_1e-3"] == 5
     assert abs(out["determined_max"] - 3e-4) < 1e-9 and abs(out["max"] - 0.5) < 1e-9
     assert out["best_goal_gpu"] == out["best_goal_oracle"] == 4
